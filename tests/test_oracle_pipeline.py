@@ -1,0 +1,274 @@
+"""Whole-pipeline pins of the oracle against what the paper fixes:
+no false positives / false types (Section III-B, Table II), lost extrema
+restored (Section V, discussion of Table II), the relaxed bound <= 2e
+(Section V, datasets table), and the special cases of Section IV-B."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from np_ref import MAX, MIN, R, SAD, classify_np, face_neighbour_same_bin, quantize_np, recon_np
+
+from paper_2602_17552_amd import datagen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _roundtrip(ora, f, eb, mode="abs", **kw):
+    rc, s = ora.compress(f, eb, mode, **kw)
+    assert rc == ora.OK
+    rc, info = ora.inspect(s)
+    rc2, rec, st = ora.decompress(s, f.shape)
+    assert rc2 == ora.OK
+    return s, info, rec, st
+
+
+def _fields():
+    yield "bumps", datagen.gaussian_bumps_2d(96, 130, 12, seed=3, noise_sd=1e-3), 1e-3, "rel"
+    yield "waves", datagen.sinusoids_2d(90, 180, 16, seed=4, noise_sd=1e-2), 1e-3, "rel"
+    yield "noise", datagen.noise((77, 91), seed=5), 0.3, "abs"
+    yield "grf3d", datagen.grf_3d(20, 24, 28, seed=6), 1e-3, "abs"
+    yield "noise3d", datagen.noise((9, 17, 23), seed=7), 0.2, "abs"
+    yield "row", datagen.noise((1, 300), seed=8), 0.1, "abs"
+
+
+@pytest.mark.parametrize("name,f,eb,mode", list(_fields()), ids=[x[0] for x in _fields()])
+def test_invariants(ora, name, f, eb, mode):
+    s, info, rec, st = _roundtrip(ora, f, eb, mode)
+    e = info["e"]
+    ev = ora.eval_topology(f, rec)
+    # Section III-B / Table II: no false positives, no false types
+    assert ev["FP"] == 0 and ev["FT"] == 0
+    # lost extrema fully resolved unless the error budget forbade the move
+    assert ev["FN_min"] + ev["FN_max"] == st["budget_skips"]
+    # relaxed bound: every point within 2e of the original
+    err = np.abs(rec.astype(np.float64) - f.astype(np.float64))
+    assert err.max() <= 2 * e
+    # points the decompressor did not move stay at the bin centre (<= e)
+    q = quantize_np(f, e)
+    moved = rec != recon_np(q, e)
+    assert np.all(err[~moved] <= e * (1 + 2 ** -22))
+    # FN never exceeds plain SZp's on the same bins
+    szp = ora.eval_topology(f, recon_np(q, e))
+    assert ev["FN"] <= szp["FN"]
+
+
+@pytest.mark.parametrize("name,f,eb,mode", list(_fields()), ids=[x[0] for x in _fields()])
+def test_rank_metadata_marks_flattened_points(ora, name, f, eb, mode):
+    """delta > 0 exactly at critical points that plain SZp flattens (class in
+    the bin-centre field differs from the original class)."""
+    rc, info = ora.inspect(ora.compress(f, eb, mode)[1])
+    e = info["e"]
+    q = quantize_np(f, e)
+    lab, delta = ora.labels_ranks(f, q.astype(np.int32))
+    assert np.array_equal(lab, classify_np(f))
+    lost_by_class = (lab != R) & (classify_np(recon_np(q, e)) != lab)
+    lost_by_bin = (lab != R) & face_neighbour_same_bin(q)
+    assert np.array_equal(lost_by_class, lost_by_bin)
+    assert np.array_equal(delta > 0, lost_by_class)
+    assert np.all(delta[lab == SAD] <= 1)
+
+
+def _brute_ranks(f, q, lab, lost, scope):
+    flat_f, flat_q, flat_l, flat_lost = f.reshape(-1), q.reshape(-1), lab.reshape(-1), lost.reshape(-1)
+    n = flat_f.size
+    out = np.zeros(n, np.int64)
+    for p in range(n):
+        if not flat_lost[p]:
+            continue
+        if flat_l[p] == SAD:
+            out[p] = 1
+            continue
+        lo, hi = (p // 64 * 64, min(n, p // 64 * 64 + 64)) if scope == 0 else (0, n)
+        cnt = 1
+        for j in range(lo, hi):
+            if flat_lost[j] and flat_l[j] == flat_l[p] and flat_q[j] == flat_q[p]:
+                if (flat_f[j] < flat_f[p]) if flat_l[p] == MAX else (flat_f[j] > flat_f[p]):
+                    cnt += 1
+        out[p] = cnt
+    return out.reshape(f.shape)
+
+
+@pytest.mark.parametrize("scope", [0, 1])
+def test_ranks_brute_force(ora, scope):
+    f = datagen.noise((23, 37), seed=12)
+    e = np.float32(0.4)
+    q = quantize_np(f, e).astype(np.int32)
+    lab, delta = ora.labels_ranks(f, q, rank_scope=scope)
+    lost = (lab != R) & face_neighbour_same_bin(q)
+    assert np.array_equal(delta, _brute_ranks(f, q, lab, lost, scope))
+
+
+def test_fig5_relative_order(ora):
+    g = json.load(open(os.path.join(GOLDEN, "fig5_relative_order.json")))
+    f = np.array(g["field"], np.float32)
+    e = ora.eps_float(g["eps"])
+    q = quantize_np(f, e).astype(np.int32)
+    assert np.all(q == 1)  # both maxima and all neighbours in bin 1
+    lab, delta = ora.labels_ranks(f, q)
+    (a, b), (c, d) = g["m1"], g["m2"]
+    assert lab[a, b] == MAX and lab[c, d] == MAX
+    assert delta[a, b] == g["expected_delta_m1"] and delta[c, d] == g["expected_delta_m2"]
+    s, info, rec, st = _roundtrip(ora, f, g["eps"], "abs")
+    # order restored: M1 < M2 and both maxima again
+    assert rec[a, b] < rec[c, d]
+    c2 = ora.classify(rec)
+    assert c2[a, b] == MAX and c2[c, d] == MAX
+
+
+def test_fig2_stencil_output(ora):
+    g = json.load(open(os.path.join(GOLDEN, "fig2_flattened_max.json")))
+    f = np.array(g["field"], np.float32)
+    s, info, rec, st = _roundtrip(ora, f, g["eps"], "abs")
+    two_e = np.float32(2) * np.float32(info["e"])
+    assert rec[1, 1] == np.nextafter(two_e, np.float32(np.inf))
+    assert float(rec[1, 1]) == float(g["expected_output_centre"].split("=")[-1])
+    assert ora.classify(rec)[1, 1] == MAX
+
+
+def test_single_bin_field(ora):
+    """Section IV-B (3): when every neighbour falls in the same bin no convex
+    update can restore a saddle; extrema are still restored by the stencil.
+    A noise half (many extrema) sits above a smooth saddle surface half."""
+    noise = (0.4 * datagen.noise((40, 50), seed=21, dist="uniform")).astype(np.float32)
+    yy, xx = np.mgrid[0:40, 0:50].astype(np.float64)
+    saddle = (1e-3 * ((xx - 25.3) ** 2 - (yy - 19.6) ** 2)).astype(np.float32)
+    f = np.ascontiguousarray(np.concatenate([noise, saddle], axis=0))
+    s, info, rec, st = _roundtrip(ora, f, 10.0, "abs", rbf_policy=1)  # one bin holds everything
+    assert np.all(quantize_np(f, info["e"]) == 0)
+    ev = ora.eval_topology(f, rec)
+    assert ev["FN_min"] == 0 and ev["FN_max"] == 0
+    lab = classify_np(f)
+    out = classify_np(rec)
+    moved_ext = ((lab == MIN) | (lab == MAX)) & (rec != 0)
+    r = info["k"] // 2
+    ny, nx = f.shape
+    flat_window = 0
+    for y, x in zip(*np.nonzero(lab == SAD)):
+        win = [(y + dy, x + dx) for dy in range(-r, r + 1) for dx in range(-r, r + 1)
+               if dy * dy + dx * dx <= r * r and 0 <= y + dy < ny and 0 <= x + dx < nx]
+        if not any(moved_ext[p] for p in win):
+            # the whole window still sits at the shared bin centre
+            assert out[y, x] == R and rec[y, x] == 0
+            flat_window += 1
+    assert flat_window > 0
+    assert ev["FN"] >= flat_window
+
+
+def test_wide_gap_field_is_plain_szp(ora):
+    """Section III-B: with every neighbour gap above 2e no critical point is
+    lost, so the output equals the plain SZp reconstruction."""
+    rng = np.random.default_rng(3)
+    f = (rng.permutation(40 * 40).reshape(40, 40) * 10.0).astype(np.float32)
+    s, info, rec, st = _roundtrip(ora, f, 1.0, "abs")
+    q = quantize_np(f, info["e"])
+    assert np.array_equal(rec, recon_np(q, info["e"]))
+    assert ora.eval_topology(f, rec)["FN"] == 0
+    rc, plain = ora.compress(f, 1.0, "abs", topo=False)
+    rc, rec0, _ = ora.decompress(plain, f.shape)
+    assert np.array_equal(rec0, rec)
+
+
+def test_k3_candidate_is_mean_of_face_neighbours(ora):
+    """For k_size = 3 the window is the four face neighbours at distance 1, all
+    with the same weight, so Eq. (2) reduces to their mean (computed in
+    double, rounded once)."""
+    e = 0.5
+    # saddle at the centre: vertical neighbours higher, horizontal lower; the
+    # right neighbour shares the centre's bin so plain SZp flattens it
+    f = np.array([[9, 9, 2.6, 9, 9],
+                  [9, 9, 0.9, 9, 9],
+                  [-9, -1.0, 0.2, 0.1, -9],
+                  [9, 9, 0.9, 9, 9],
+                  [9, 9, 2.6, 9, 9]], np.float32)
+    assert ora.classify(f)[2, 2] == SAD
+    s, info, rec, st = _roundtrip(ora, f, e, "abs", rbf_policy=1)
+    assert info["k"] == 3
+    q = quantize_np(f, info["e"])
+    base = recon_np(q, info["e"])
+    assert base[2, 2] == base[2, 3]  # flattened by plain SZp
+    nbr = [base[1, 2], base[3, 2], base[2, 1], base[2, 3]]
+    w = float(np.float32(np.exp(-1.0 / (2 * 0.5 ** 2))))
+    num = 0.0
+    for v in [base[1, 2], base[2, 1], base[2, 3], base[3, 2]]:  # (dy, dx) lexicographic
+        num = num + w * float(v)
+    mean = np.float32(num / (4 * w))
+    assert abs(float(mean) - float(np.mean(np.array(nbr, np.float64)))) < 1e-6
+    assert rec[2, 2] == mean
+    assert ora.classify(rec)[2, 2] == SAD
+
+
+def test_plain_szp_mode(ora):
+    f = datagen.gaussian_bumps_2d(50, 60, 5, seed=9)
+    rc, s = ora.compress(f, 1e-3, "rel", topo=False)
+    rc, info = ora.inspect(s)
+    rc, rec, st = ora.decompress(s, f.shape)
+    assert np.array_equal(rec, recon_np(quantize_np(f, info["e"]), info["e"]))
+    assert info["topo"] == 0 and info["seg_len"][4] == 0
+
+
+def test_rbf_parameter_rule(ora):
+    """k_size 7 / 5 / 3 from the mean block width (smooth -> larger kernel)."""
+    smooth = datagen.gaussian_bumps_2d(64, 64, 3, seed=1, noise_sd=0.0)
+    rough = datagen.noise((64, 64), seed=2)
+    ks = []
+    for f, eb in [(smooth, 1e-2), (smooth, 3e-4), (rough, 1e-4)]:
+        rc, s = ora.compress(f, eb, "rel")
+        rc, info = ora.inspect(s)
+        nb = info["nb"]
+        k = 7 if info["wdata"] <= nb else (5 if info["wdata"] <= 3 * nb else 3)
+        assert info["k"] == k
+        ks.append(k)
+        w = ora.rbf_weights(info["sigma"])
+        assert w[0] == 1.0
+    assert ks[-1] == 3
+
+
+def test_rbf_weights_against_decimal_exp(ora):
+    """w[d2] = float32(exp(-d2 / (2 sigma^2))), checked against exp evaluated
+    with 40-digit decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    for sigma in (0.5, 0.75, 1.0):
+        w = ora.rbf_weights(sigma)
+        for d2 in range(10):
+            x = (-Decimal(d2) / (2 * Decimal(str(sigma)) ** 2)).exp()
+            assert w[d2] == np.float32(float(x))
+
+
+def test_errors(ora):
+    f = np.ones((4, 4), np.float32)
+    assert ora.compress(f, 0.0, "abs")[0] == ora.E_INVALID_ARG
+    assert ora.compress(f, -1.0, "abs")[0] == ora.E_INVALID_ARG
+    g = f.copy()
+    g[1, 2] = np.nan
+    assert ora.compress(g, 0.1, "abs")[0] == ora.E_NONFINITE
+    g[1, 2] = np.inf
+    assert ora.compress(g, 0.1, "abs")[0] == ora.E_NONFINITE
+    assert ora.compress(f * 1e30, 1e-3, "abs")[0] == ora.E_RANGE
+    assert ora.compress(f, 1e-35, "abs")[0] == ora.E_RANGE  # e below 2^-100
+    # constant field in relative mode: the bound falls back to eb itself
+    rc, s = ora.compress(f, 1e-3, "rel")
+    assert rc == ora.OK and ora.inspect(s)[1]["eps_d"] == 1e-3
+
+
+def test_corrupt_streams_rejected(ora):
+    f = datagen.noise((30, 40), seed=3)
+    rc, s = ora.compress(f, 0.05, "abs")
+    assert ora.decompress(s[:100], f.shape)[0] == ora.E_CORRUPT
+    assert ora.decompress(s[:-8], f.shape)[0] == ora.E_CORRUPT
+    assert ora.decompress(s, (10, 10))[0] == ora.E_CAPACITY
+    rng = np.random.default_rng(0)
+    for off in range(0, 384):  # header fields and their checksum
+        t = s.copy()
+        t[off] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        assert ora.decompress(t, f.shape)[0] == ora.E_CORRUPT, off
+    # widths out of range or inconsistent with the constant-block bitmap
+    _, info = ora.inspect(s)
+    t = s.copy()
+    t[info["seg_off"][1]] = 40
+    assert ora.decompress(t, f.shape)[0] == ora.E_CORRUPT
+    t = s.copy()
+    t[info["seg_off"][0]] ^= 1
+    assert ora.decompress(t, f.shape)[0] == ora.E_CORRUPT
