@@ -361,16 +361,16 @@ static double get_f64(const uint8_t *b, size_t off) { double v; memcpy(&v, b + o
 
 static uint64_t align8(uint64_t x) { return (x + 7) & ~(uint64_t)7; }
 
-/* 64-bit FNV-1a (Fowler-Noll-Vo) over the header fields, stored after them so
- * that any corrupted header byte is detected. */
+/* Adler-32 (RFC 1950) over the header fields, stored after them so that any
+ * corrupted header byte is detected. */
 #define HDR_SUMMED 376
-static uint64_t fnv1a64(const uint8_t *b, size_t n) {
-  uint64_t h = 14695981039346656037ULL;
+static uint32_t adler32(const uint8_t *b, size_t n) {
+  uint32_t a = 1, s = 0;
   for (size_t i = 0; i < n; i++) {
-    h ^= b[i];
-    h *= 1099511628211ULL;
+    a = (a + b[i]) % 65521u;
+    s = (s + a) % 65521u;
   }
-  return h;
+  return (s << 16) | a;
 }
 
 /* Lengths and offsets of the 13 segments: the fixed-size parts first (their
@@ -527,7 +527,7 @@ int ora_compress(const float *f, int ndim, const uint64_t dims[3], int eb_mode,
     put_u64(out, 264 + 8 * (size_t)s, len[s]);
   }
 
-  put_u64(out, HDR_SUMMED, fnv1a64(out, HDR_SUMMED));
+  put_u32(out, HDR_SUMMED, adler32(out, HDR_SUMMED));
 
   /* parts (1)-(5) of the bin indices */
   encode_stream(q, n, out, off, SEG_S1, SEG_S2, SEG_S3, SEG_S4, SEG_X1, SEG_S5);
@@ -560,7 +560,8 @@ typedef struct {
 static int parse_header(const uint8_t *in, size_t in_size, hdr_t *h) {
   if (!in || in_size < HDR_BYTES) return ORA_E_CORRUPT;
   if (memcmp(in, "TSZ1", 4) != 0 || get_u16(in, 4) != 1) return ORA_E_CORRUPT;
-  if (get_u64(in, HDR_SUMMED) != fnv1a64(in, HDR_SUMMED)) return ORA_E_CORRUPT;
+  if (get_u32(in, HDR_SUMMED) != adler32(in, HDR_SUMMED) || get_u32(in, HDR_SUMMED + 4) != 0)
+    return ORA_E_CORRUPT;
   h->ndim = in[6];
   if (h->ndim != 2 && h->ndim != 3) return ORA_E_CORRUPT;
   if (in[7] & ~3u) return ORA_E_CORRUPT;

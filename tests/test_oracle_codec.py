@@ -91,3 +91,13 @@ def test_chunk_index_matches_widths(ora):
     bitmap = s[info["seg_off"][0]: info["seg_off"][0] + info["seg_len"][0]]
     const = np.array([(bitmap[b >> 3] >> (b & 7)) & 1 for b in range(nb)])
     assert np.array_equal(const, (widths == 0).astype(int))
+
+
+def test_header_checksum_is_adler32(ora):
+    """The header's bytes [0, 376) are covered by an Adler-32 (RFC 1950)
+    checksum stored at byte 376; zlib's implementation is the reference."""
+    import zlib
+    f = np.random.default_rng(6).standard_normal((20, 30)).astype(np.float32)
+    rc, s = ora.compress(f, 0.01, "rel")
+    assert int(s[376:380].view(np.uint32)[0]) == zlib.adler32(bytes(s[:376]))
+    assert not s[380:512].any()
