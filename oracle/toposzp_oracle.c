@@ -469,6 +469,9 @@ int ora_compress(const float *f, int ndim, const uint64_t dims[3], int eb_mode,
       if (f[i] < vmin) vmin = f[i];
       if (f[i] > vmax) vmax = f[i];
     }
+    /* a zero extreme is stored as +0 whichever signed zero came first */
+    if (vmin == 0.0f) vmin = 0.0f;
+    if (vmax == 0.0f) vmax = 0.0f;
     if (vmax > vmin) eps_d = eb * ((double)vmax - (double)vmin);
   }
   float e = ora_eps_float(eps_d);
