@@ -1,0 +1,230 @@
+"""TopoSZp on MI355X: Python binding of libtoposzp.so.
+
+Argument marshalling only: every step of compression and decompression runs in
+the library's HIP kernels.  PyTorch provides device memory and the current
+stream.  Importing the package does not load the library; the first call does,
+and raises if the library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtoposzp.so")
+
+OK, E_INVALID_ARG, E_NONFINITE, E_RANGE, E_CAPACITY, E_CORRUPT, E_DEVICE, E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+EB_ABS, EB_REL = 0, 1
+SYMBOLS = [
+    "toposzp_version", "toposzp_strerror", "toposzp_compress_bound", "toposzp_workspace_size",
+    "toposzp_workspace_init", "toposzp_compress", "toposzp_decompress", "toposzp_compress_sync",
+    "toposzp_decompress_sync", "toposzp_inspect", "toposzp_decompress_stats",
+    "toposzp_set_timing", "toposzp_kernel_times",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("rank_scope", C.c_int32), ("rbf_policy", C.c_int32),
+                ("max_rounds", C.c_int32), ("topo", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("topo", C.c_int32), ("rank_scope", C.c_int32),
+                ("eb_mode", C.c_int32), ("k_size", C.c_int32), ("max_rounds", C.c_int32),
+                ("dims", C.c_uint64 * 3), ("n", C.c_uint64), ("nblocks", C.c_uint64),
+                ("total_bytes", C.c_uint64), ("data_planes", C.c_uint64),
+                ("rank_planes", C.c_uint64), ("eb", C.c_double), ("eps", C.c_double),
+                ("e", C.c_float), ("vmin", C.c_float), ("vmax", C.c_float),
+                ("sigma", C.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtoposzp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        u64p = C.POINTER(C.c_uint64)
+        vp = C.c_void_p
+        L.toposzp_version.restype = C.c_int
+        L.toposzp_strerror.restype = C.c_char_p
+        L.toposzp_strerror.argtypes = [C.c_int]
+        L.toposzp_compress_bound.restype = C.c_size_t
+        L.toposzp_compress_bound.argtypes = [C.c_uint32, u64p]
+        L.toposzp_workspace_size.restype = C.c_size_t
+        L.toposzp_workspace_size.argtypes = [C.c_uint32, u64p]
+        L.toposzp_workspace_init.restype = C.c_int
+        L.toposzp_workspace_init.argtypes = [vp, C.c_size_t, vp]
+        L.toposzp_compress.restype = C.c_int
+        L.toposzp_compress.argtypes = [vp, C.c_uint32, u64p, C.c_int, C.c_double,
+                                       C.POINTER(Params), vp, C.c_size_t, vp, C.c_size_t,
+                                       vp, vp, vp]
+        L.toposzp_decompress.restype = C.c_int
+        L.toposzp_decompress.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp, vp]
+        L.toposzp_compress_sync.restype = C.c_int
+        L.toposzp_compress_sync.argtypes = [vp, C.c_uint32, u64p, C.c_int, C.c_double,
+                                            C.POINTER(Params), vp, C.c_size_t, vp, C.c_size_t,
+                                            C.POINTER(C.c_uint64), vp]
+        L.toposzp_decompress_sync.restype = C.c_int
+        L.toposzp_decompress_sync.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.toposzp_inspect.restype = C.c_int
+        L.toposzp_inspect.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(Info)]
+        L.toposzp_decompress_stats.restype = C.c_int
+        L.toposzp_decompress_stats.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        L.toposzp_set_timing.restype = C.c_int
+        L.toposzp_set_timing.argtypes = [C.c_int]
+        L.toposzp_kernel_times.restype = C.c_int
+        L.toposzp_kernel_times.argtypes = [C.POINTER(C.c_float), C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dims(shape):
+    arr = (C.c_uint64 * 3)(1, 1, 1)
+    for k, d in enumerate(shape):
+        arr[k] = int(d)
+    return arr
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def strerror(status: int) -> str:
+    return lib().toposzp_strerror(int(status)).decode()
+
+
+def compress_bound(shape) -> int:
+    return int(lib().toposzp_compress_bound(len(shape), _dims(shape)))
+
+
+def workspace_size(shape) -> int:
+    return int(lib().toposzp_workspace_size(len(shape), _dims(shape)))
+
+
+class Workspace:
+    """Device workspace sized for fields up to `shape` (compress and
+    decompress), cleared once on creation."""
+
+    def __init__(self, shape, device="cuda", stream=None):
+        import torch
+        nbytes = workspace_size(shape)
+        if nbytes == 0:
+            raise ValueError(f"invalid field shape {shape}")
+        self.shape = tuple(shape)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+        rc = lib().toposzp_workspace_init(C.c_void_p(self.buf.data_ptr()), nbytes, _stream(stream))
+        if rc != OK:
+            raise RuntimeError(strerror(rc))
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+def _params(topo=True, rank_scope=0, rbf_policy=0, max_rounds=16):
+    return Params(64, int(rank_scope), int(rbf_policy), int(max_rounds), int(bool(topo)))
+
+
+def compress_async(field, eb, mode="rel", ws=None, out=None, size=None, status=None,
+                   stream=None, **params):
+    """Enqueues compression of a float32 CUDA tensor.  Returns
+    (out uint8 tensor, size uint64[1] tensor, status int32[1] tensor); the
+    first size[0] bytes of out are the stream once the call has completed."""
+    import torch
+    if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
+        raise TypeError("field must be a contiguous float32 CUDA tensor")
+    shape = tuple(field.shape)
+    ws = ws or Workspace(shape, field.device, stream)
+    if out is None:
+        out = torch.empty(compress_bound(shape), dtype=torch.uint8, device=field.device)
+    if size is None:
+        size = torch.zeros(1, dtype=torch.int64, device=field.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=field.device)
+    p = _params(**params)
+    rc = lib().toposzp_compress(C.c_void_p(field.data_ptr()), len(shape), _dims(shape),
+                                EB_REL if mode == "rel" else EB_ABS, float(eb), C.byref(p),
+                                ws.ptr, ws.nbytes, C.c_void_p(out.data_ptr()), out.numel(),
+                                C.c_void_p(size.data_ptr()), C.c_void_p(status.data_ptr()),
+                                _stream(stream))
+    if rc != OK:
+        raise RuntimeError(f"toposzp_compress: {strerror(rc)} ({rc})")
+    return out, size, status
+
+
+def compress(field, eb, mode="rel", ws=None, stream=None, **params):
+    """Synchronous compression: returns (status, stream bytes as a uint8 CUDA
+    tensor view of the output buffer)."""
+    import torch
+    out, size, status = compress_async(field, eb, mode, ws=ws, stream=stream, **params)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    st = int(status.item())
+    return st, out[: int(size.item())] if st == OK else out[:0]
+
+
+def decompress_async(stream_bytes, nbytes, out, ws=None, status=None, stream=None):
+    """Enqueues decompression into the float32 CUDA tensor `out` (its numel is
+    the capacity).  Returns the status int32[1] tensor."""
+    import torch
+    if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float32 CUDA tensor")
+    ws = ws or Workspace(tuple(out.shape), out.device, stream)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=out.device)
+    rc = lib().toposzp_decompress(C.c_void_p(stream_bytes.data_ptr()), int(nbytes),
+                                  C.c_void_p(out.data_ptr()), out.numel(), ws.ptr, ws.nbytes,
+                                  C.c_void_p(status.data_ptr()), _stream(stream))
+    if rc != OK:
+        raise RuntimeError(f"toposzp_decompress: {strerror(rc)} ({rc})")
+    return status
+
+
+def decompress(stream_bytes, shape, ws=None, nbytes=None, stream=None):
+    """Synchronous decompression: returns (status, float32 CUDA tensor)."""
+    import torch
+    out = torch.empty(tuple(shape), dtype=torch.float32, device=stream_bytes.device)
+    nb = stream_bytes.numel() if nbytes is None else nbytes
+    status = decompress_async(stream_bytes, nb, out, ws=ws, stream=stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return int(status.item()), out
+
+
+def decompress_stats(ws, stream=None):
+    arr = (C.c_int64 * 5)()
+    rc = lib().toposzp_decompress_stats(ws.ptr, arr, _stream(stream))
+    if rc != OK:
+        raise RuntimeError(strerror(rc))
+    keys = ["rounds", "commits", "queued", "stencil_moves", "budget_skips"]
+    return {k: int(arr[i]) for i, k in enumerate(keys)}
+
+
+def inspect(header: bytes):
+    info = Info()
+    rc = lib().toposzp_inspect(header, len(header), C.byref(info))
+    if rc != OK:
+        return rc, None
+    d = {k: getattr(info, k) for k, _ in Info._fields_}
+    d["dims"] = [int(x) for x in info.dims]
+    return rc, d
+
+
+def set_timing(enable: bool):
+    lib().toposzp_set_timing(int(bool(enable)))
+
+
+def kernel_times():
+    """ms of the last call's kernels: range, encode, finalize, decode, refine
+    (-1 where a kernel did not run); valid after the stream is synchronised."""
+    arr = (C.c_float * 5)()
+    k = lib().toposzp_kernel_times(arr, 5)
+    names = ["range", "encode", "finalize", "decode", "refine"]
+    return {names[i]: float(arr[i]) for i in range(k)}

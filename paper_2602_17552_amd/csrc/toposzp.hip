@@ -1,0 +1,1542 @@
+// libtoposzp: TopoSZp compression and decompression on MI355X (gfx950).
+//
+// Kernels (one wave of 64 lanes handles one 64-point block, lane = point):
+//   range_kernel     relative-bound pass: min/max of the field, finiteness.
+//   encode_kernel    one workgroup per chunk of 64 blocks: critical point
+//                    detection and ranks on the original values, exact
+//                    quantization, 1-D differences, per-block bit widths,
+//                    sign and bit-plane ballots, 2-bit labels; a decoupled
+//                    look-back scan over chunks places the variable-size
+//                    payload, which is written coalesced from LDS.
+//   finalize_kernel  header, rank payload move, status, workspace reset.
+//   decode_kernel    one workgroup per chunk: planes -> residuals -> in-wave
+//                    prefix sum -> bin centres, labels and ranks, the extrema
+//                    stencil (pointwise: a flattened extremum moves delta
+//                    float steps off its bin centre), flattened saddles queued.
+//   refine_kernel    cooperative: colour-phased RBF rounds over the queue,
+//                    grid barriers between phases, until a round commits
+//                    nothing.
+//
+// Method: Section IV of the paper (compression IV-A, decompression IV-B);
+// readings of the points the paper leaves open are stated where used.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "toposzp.h"
+
+namespace {
+
+constexpr int kB = 64;                 // points per block (one wave)
+constexpr int kQMax = 4194303;         // |q| <= 2^22 - 1
+constexpr int kHdr = 512;              // header bytes
+constexpr int kSummed = 376;           // header bytes covered by Adler-32
+constexpr int kMaxWData = 23;          // widest value residual: 2 * kQMax < 2^23
+constexpr int kMaxWRankBlk = 7;        // block-scope ranks lie in [0, 64]
+constexpr int kMaxWRankAny = 31;       // field-scope ranks lie in [0, N]
+constexpr int kNSeg = 13;
+constexpr int kMaxRounds = 65535;
+constexpr int kSingleMax = 2048;       // refine with one workgroup up to this
+enum { S1, S2, S3, S4, S6, R1, R2, R3, R4, X1, X2, S5, R5 };
+enum { CLS_R = 0, CLS_MIN = 1, CLS_SAD = 2, CLS_MAX = 3 };
+
+// ---------------------------------------------------------------------------
+// Workspace layout.  Control block first, then the per-round commit counters
+// (decompression), then a region shared by the compressor (look-back words,
+// staged rank planes) and the decompressor (saddle queue).
+
+struct Plan {                 // decode -> refine hand-off
+  int valid, topo, ndim, k, ncol, max_rounds, twostep, pad;
+  int n, nx, ny, nz;
+  float e;
+  float w[10];
+  uint64_t s6_off;
+  uint64_t wl_cap;
+};
+
+struct Ctrl {
+  // compression
+  unsigned ticket;            // chunk tickets (dispatch order)
+  unsigned vmin_u, vmax_u;    // order-preserving keys of the range
+  unsigned cflags;            // 1 non-finite, 2 bound out of range, 4 |q| too big
+  unsigned long long tot_data, tot_rank;
+  unsigned done_fin;
+  unsigned timeout;            // a bounded wait gave up (reported as E_DEVICE)
+  unsigned pad0[6];
+  // decompression
+  unsigned dflags;            // 1 corrupt, 2 capacity
+  unsigned wl_count;
+  unsigned bar;               // grid barrier arrivals
+  unsigned done_ref;
+  unsigned rounds_used;
+  unsigned pad1[3];
+  unsigned long long st_moves, st_skips;
+  unsigned long long stats[5];// last decompression: rounds, commits, queued, moves, skips
+  Plan plan;
+};
+static_assert(sizeof(Ctrl) <= 1024, "control block");
+
+constexpr size_t kCtrlBytes = 1024;
+constexpr size_t kRcOff = kCtrlBytes;                              // u32[kMaxRounds + 2]
+constexpr size_t kRegionOff = (kRcOff + 4 * (kMaxRounds + 2) + 255) & ~size_t(255);
+constexpr unsigned kSpinLimit = 1u << 22;  // bounded waits: ~seconds, then E_DEVICE
+
+// The compressor's look-back words sit in their own area right after the
+// counters, sized from the workspace size so that no field that fits the
+// workspace can need more (a workspace of W bytes serves at most W/10
+// points, i.e. W/40960 + 1 chunks); the rank-plane staging (compression) and
+// the saddle queue (decompression) share the area after it.
+__host__ __device__ constexpr uint64_t lookback_bytes(uint64_t ws_bytes) {
+  return ((ws_bytes / 40960 + 2) * 8 + 255) & ~uint64_t(255);
+}
+__host__ __device__ constexpr uint64_t shared_off(uint64_t ws_bytes) {
+  return kRegionOff + lookback_bytes(ws_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+
+__device__ __forceinline__ int fkey(float x) {
+  // order-preserving integer key of a float; -0 and +0 share key 0
+  int b = __float_as_int(x);
+  return b >= 0 ? b : (int)(0x80000000u - (unsigned)b);
+}
+__device__ __forceinline__ float key2f(long long k) {
+  if (k > 0x7F800000LL) k = 0x7F800001LL;     // past +inf: not a finite value
+  if (k < -0x7F800000LL) k = -0x7F800001LL;
+  unsigned b = k >= 0 ? (unsigned)k : 0x80000000u + (unsigned)(-k);
+  return __int_as_float((int)b);
+}
+__device__ __forceinline__ unsigned ukey(float x) { return (unsigned)fkey(x) ^ 0x80000000u; }
+__device__ __forceinline__ float ukey2f(unsigned u) { return key2f((int)(u ^ 0x80000000u)); }
+
+__device__ __forceinline__ float round_down_f(double d) {
+  float f = (float)d;
+  if ((double)f > d) f = __int_as_float(__float_as_int(f) - 1);  // d > 0 here
+  return f;
+}
+
+// Bin index of a: the unique q with (2q-1)e <= a < (2q+1)e.  A float estimate
+// is corrected once by an exact test: with |q| < 2^23 the product q*2e is
+// exact in double and a - q*2e is exact near the bin edges, so the two
+// comparisons with +-e decide the edges exactly.
+__device__ __forceinline__ int quantize(float a, float inv2e, double ed) {
+  float t = rintf(a * inv2e);
+  t = fminf(fmaxf(t, -4194305.0f), 4194305.0f);
+  int q = (int)t;
+  double d = (double)a - (double)q * (2.0 * ed);
+  q += (d >= ed) ? 1 : ((d < -ed) ? -1 : 0);
+  return q;
+}
+
+// Class from the six face neighbours [x-, x+, y-, y+, z-, z+]; axes of
+// extent 1 carry no neighbours and take no part in the saddle test.
+__device__ __forceinline__ int classify6(float a, const float nb[6], const bool av[6],
+                                         const bool deg[3]) {
+  int navail = 0, up = 0, dn = 0;
+  bool all_gt = true, all_lt = true, pairs_ok = true;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (deg[ax]) continue;
+    const bool hl = av[2 * ax], hh = av[2 * ax + 1];
+    const bool lg = hl && nb[2 * ax] > a, ll = hl && nb[2 * ax] < a;
+    const bool hg = hh && nb[2 * ax + 1] > a, hs = hh && nb[2 * ax + 1] < a;
+    navail += (int)hl + (int)hh;
+    if (hl && !lg) all_gt = false;
+    if (hl && !ll) all_lt = false;
+    if (hh && !hg) all_gt = false;
+    if (hh && !hs) all_lt = false;
+    if (!(hl && hh)) pairs_ok = false;
+    else if (lg && hg) ++up;
+    else if (ll && hs) ++dn;
+    else pairs_ok = false;
+  }
+  if (navail == 0) return CLS_R;
+  if (all_gt) return CLS_MIN;
+  if (all_lt) return CLS_MAX;
+  if (pairs_ok && up > 0 && dn > 0) return CLS_SAD;
+  return CLS_R;
+}
+
+__device__ __forceinline__ unsigned wave_max_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o);
+    if (lane >= o) v = (int)((unsigned)v + (unsigned)t);
+  }
+  return v;
+}
+__device__ __forceinline__ unsigned mbcnt(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// B + LZ + BE of one 64-value block held one value per lane: residuals
+// r_0 = 0, r_i = v_i - v_{i-1}; width = bit length of max |r_i|; the sign and
+// each bit plane are one 64-bit ballot.  Planes go to dst[0..w) (LDS).
+template <int MAXW>
+__device__ __forceinline__ int encode_block(int v, int lane, unsigned long long* dst,
+                                            unsigned long long& sign, int& first, bool& over) {
+  const int prev = __shfl_up(v, 1);
+  long long r = (long long)v - (long long)prev;
+  if (lane == 0) r = 0;
+  sign = __ballot(r < 0);
+  const unsigned mag = (unsigned)(r < 0 ? -r : r);
+  const unsigned mx = wave_max_u(mag);
+  const int w0 = mx ? 32 - __clz((int)mx) : 0;
+  int w = w0;
+  if (w > MAXW) { over = true; w = MAXW; }
+  unsigned long long mine = 0;
+  for (int j = 0; j < w; ++j) {
+    const unsigned long long pl = __ballot((mag >> j) & 1u);
+    if (lane == j) mine = pl;
+  }
+  if (lane < w) dst[lane] = mine;
+  first = __builtin_amdgcn_readlane(v, 0);
+  return w;
+}
+
+// Inverse: planes (uniform addresses) -> magnitudes -> signed residuals ->
+// in-wave inclusive prefix sum.
+__device__ __forceinline__ int decode_block(const uint8_t* planes, int w, int first,
+                                            unsigned long long sign, int lane) {
+  unsigned mag = 0;
+  for (int j = 0; j < w; ++j) {
+    const unsigned long long pl = *(const unsigned long long*)(planes + 8 * (size_t)j);
+    mag |= (unsigned)((pl >> lane) & 1ull) << j;
+  }
+  int r = ((sign >> lane) & 1ull) ? (int)(0u - mag) : (int)mag;
+  if (lane == 0) r = first;
+  return wave_incl_scan(r, lane);
+}
+
+__device__ __forceinline__ unsigned long long ld_acq(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel arguments.
+
+struct Geom {
+  int n, nx, ny, nz, ndim;
+};
+
+struct EncArgs {
+  const float* f;
+  uint8_t* out;
+  uint8_t* ws;
+  uint64_t ws_bytes;
+  Geom g;
+  int nb, nch, topo, eb_mode, rbf_policy, max_rounds;
+  double eb;
+  float e_abs;
+  uint64_t off[kNSeg], len[kNSeg];
+};
+
+struct FinArgs {
+  uint8_t* out;
+  uint8_t* ws;
+  uint64_t ws_bytes;
+  uint64_t* out_size;
+  int32_t* status;
+  Geom g;
+  uint64_t dims[3];
+  int nb, nch, topo, eb_mode, rbf_policy, max_rounds;
+  double eb;
+  float e_abs;
+  uint64_t off[kNSeg], len[kNSeg];
+  float wtab[3][10];
+};
+
+struct DecArgs {
+  const uint8_t* in;
+  uint64_t in_size;
+  float* out;
+  uint64_t out_cap;
+  uint8_t* ws;
+  uint64_t ws_bytes;
+};
+
+struct RefArgs {
+  const uint8_t* in;
+  float* out;
+  uint8_t* ws;
+  uint64_t ws_bytes;
+  int32_t* status;
+};
+
+__device__ __forceinline__ Ctrl* ctrl_of(uint8_t* ws) { return reinterpret_cast<Ctrl*>(ws); }
+
+// Segment lengths and offsets: fixed-size parts first (offsets depend on the
+// block count only), the two variable-size payloads last.
+__host__ __device__ inline uint64_t seg_layout(uint64_t nb, int topo, uint64_t wdata,
+                                               uint64_t wrank, uint64_t* off, uint64_t* len) {
+  const uint64_t nch = (nb + kB - 1) / kB;
+  const uint64_t t = topo ? 1 : 0;
+  len[S1] = 8 * nch;
+  len[S2] = nb;
+  len[S3] = 8 * nb;
+  len[S4] = 4 * nb;
+  len[S6] = t * 16 * nb;
+  len[R1] = t * 8 * nch;
+  len[R2] = t * nb;
+  len[R3] = t * 8 * nb;
+  len[R4] = t * 4 * nb;
+  len[X1] = 8 * nch;
+  len[X2] = t * 8 * nch;
+  len[S5] = 8 * wdata;
+  len[R5] = t * 8 * wrank;
+  off[0] = kHdr;
+  for (int s = 1; s < kNSeg; ++s) off[s] = (off[s - 1] + len[s - 1] + 7) & ~uint64_t(7);
+  return off[kNSeg - 1] + len[kNSeg - 1];
+}
+
+// ---------------------------------------------------------------------------
+// Workspace initialisation.
+
+__global__ void ws_init_kernel(uint8_t* ws, uint64_t nbytes) {
+  const uint64_t n8 = nbytes / 8;
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(ws);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n8;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// range accumulators start at the neutral keys
+__global__ void ws_init_keys_kernel(uint8_t* ws) {
+  Ctrl* c = ctrl_of(ws);
+  c->vmin_u = 0xFFFFFFFFu;
+  c->vmax_u = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Relative-bound range pass.
+
+__global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f, int n, uint8_t* ws) {
+  __shared__ unsigned s_lo[4], s_hi[4], s_bad[4];
+  float lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int stride = gridDim.x * blockDim.x;
+  const int n4 = n / 4;
+  const float4* f4 = reinterpret_cast<const float4*>(f);
+  const bool aligned = (reinterpret_cast<uintptr_t>(f) & 15) == 0;
+  if (aligned) {
+    for (int i = blockIdx.x * blockDim.x + tid; i < n4; i += stride) {
+      const float4 v = f4[i];
+      bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+      lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+      hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+    }
+  }
+  for (int i = (aligned ? 4 * n4 : 0) + blockIdx.x * blockDim.x + tid; i < n; i += stride) {
+    const float v = f[i];
+    bad |= !isfinite(v);
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  unsigned ulo = ukey(lo), uhi = ukey(hi);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    ulo = min(ulo, (unsigned)__shfl_xor((int)ulo, o));
+    uhi = max(uhi, (unsigned)__shfl_xor((int)uhi, o));
+  }
+  const bool anybad = __ballot(bad) != 0;
+  if (lane == 0) {
+    s_lo[wv] = ulo;
+    s_hi[wv] = uhi;
+    s_bad[wv] = anybad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned a = s_lo[0], b = s_hi[0], c = s_bad[0];
+    for (int k = 1; k < (int)(blockDim.x / 64); ++k) {
+      a = min(a, s_lo[k]);
+      b = max(b, s_hi[k]);
+      c |= s_bad[k];
+    }
+    Ctrl* ct = ctrl_of(ws);
+    atomicMin(&ct->vmin_u, a);
+    atomicMax(&ct->vmax_u, b);
+    if (c) atomicOr(&ct->cflags, 1u);
+  }
+}
+
+// Absolute bound e (float) of the call, from the range pass or the host.
+__device__ __forceinline__ double bound_eps(const Ctrl* ct, int eb_mode, double eb, float& vmin,
+                                            float& vmax) {
+  vmin = 0.0f;
+  vmax = 0.0f;
+  if (eb_mode == TOPOSZP_EB_REL) {
+    vmin = ukey2f(ct->vmin_u);
+    vmax = ukey2f(ct->vmax_u);
+    if (vmax > vmin) return eb * ((double)vmax - (double)vmin);
+  }
+  return eb;
+}
+
+// ---------------------------------------------------------------------------
+// Compression.
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
+  constexpr int BPW = kB / WAVES;  // blocks per wave
+  __shared__ unsigned long long s_pd[kB][kMaxWData];
+  __shared__ unsigned long long s_pr[kB][kMaxWRankBlk];
+  __shared__ int s_wd[kB], s_wr[kB];
+  __shared__ int s_pfd[kB + 1], s_pfr[kB + 1];
+  __shared__ unsigned s_chunk;
+  __shared__ float s_e;
+  __shared__ unsigned long long s_exd, s_exr;
+  __shared__ unsigned s_flags;
+
+  Ctrl* ct = ctrl_of(a.ws);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) {
+    s_chunk = atomicAdd(&ct->ticket, 1u);
+    float e;
+    if (a.eb_mode == TOPOSZP_EB_REL) {
+      float vmin, vmax;
+      e = round_down_f(bound_eps(ct, a.eb_mode, a.eb, vmin, vmax));
+    } else {
+      e = a.e_abs;
+    }
+    s_e = e;
+    s_flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
+  }
+  __syncthreads();
+  const int c = (int)s_chunk;
+  const float e = s_e;
+  const double ed = (double)e;
+  const float inv2e = 1.0f / (2.0f * e);
+  const int n = a.g.n, nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int nxy = nx * ny;
+  const bool deg[3] = {nx < 2, ny < 2, nz < 2};
+  bool nonfinite = false, qover = false, wover = false;
+
+  for (int k = 0; k < BPW; ++k) {
+    const int lb = wv * BPW + k;
+    const int b = c * kB + lb;
+    if (b >= a.nb) {
+      if (lane == 0) {
+        s_wd[lb] = 0;
+        s_wr[lb] = 0;
+      }
+      continue;
+    }
+    const int i = b * kB + lane;
+    const bool valid = i < n;
+    const float av = valid ? a.f[i] : 0.0f;
+    nonfinite |= valid && !isfinite(av);
+
+    int lab = CLS_R, q = quantize(av, inv2e, ed);
+    bool lost = false;
+    if (a.topo && valid) {
+      const int x = i % nx, t = i / nx, y = t % ny, z = t / ny;
+      float nb[6];
+      bool avl[6];
+      avl[0] = x > 0;
+      avl[1] = x < nx - 1;
+      avl[2] = y > 0;
+      avl[3] = y < ny - 1;
+      avl[4] = z > 0;
+      avl[5] = z < nz - 1;
+      nb[0] = avl[0] ? a.f[i - 1] : 0.0f;
+      nb[1] = avl[1] ? a.f[i + 1] : 0.0f;
+      nb[2] = avl[2] ? a.f[i - nx] : 0.0f;
+      nb[3] = avl[3] ? a.f[i + nx] : 0.0f;
+      nb[4] = avl[4] ? a.f[i - nxy] : 0.0f;
+      nb[5] = avl[5] ? a.f[i + nxy] : 0.0f;
+      lab = classify6(av, nb, avl, deg);
+      if (lab != CLS_R) {
+        // flattened by plain SZp iff some face neighbour shares the bin:
+        // -e <= a_n - 2qe < e, exact in double (see quantize)
+        const double c2 = (double)q * (2.0 * ed);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          if (!avl[j]) continue;
+          const double d = (double)nb[j] - c2;
+          lost |= (d >= -ed) && (d < ed);
+        }
+      }
+    }
+    qover |= valid && (q > kQMax || q < -kQMax);
+
+    // ranks of flattened extrema among the flattened extrema of the same
+    // class and bin in this block: 1 + number less extreme
+    int delta = 0;
+    if (a.topo) {
+      const bool isext = lost && (lab == CLS_MIN || lab == CLS_MAX);
+      unsigned long long m = __ballot(isext);
+      const int ck = (q << 1) | (lab == CLS_MAX ? 1 : 0);
+      const int ok = (lab == CLS_MAX) ? fkey(av) : -fkey(av);
+      int cnt = 0;
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int ckj = __builtin_amdgcn_readlane(ck, j);
+        const int okj = __builtin_amdgcn_readlane(ok, j);
+        cnt += (ck == ckj && okj < ok) ? 1 : 0;
+      }
+      delta = lost ? (lab == CLS_SAD ? 1 : 1 + cnt) : 0;
+    }
+
+    // the last block is padded with its last value (residual 0)
+    if (b == a.nb - 1 && (n & (kB - 1))) {
+      const int last = (n - 1) - b * kB;
+      const int ql = __builtin_amdgcn_readlane(q, last);
+      const int dl = __builtin_amdgcn_readlane(delta, last);
+      if (!valid) {
+        q = ql;
+        delta = dl;
+      }
+    }
+
+    unsigned long long sign;
+    int first;
+    const int w = encode_block<kMaxWData>(q, lane, s_pd[lb], sign, first, wover);
+    uint8_t* out = a.out;
+    if (lane == 0) {
+      s_wd[lb] = w;
+      out[a.off[S2] + b] = (uint8_t)w;
+      *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = sign;
+      *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = first;
+    }
+    if (a.topo) {
+      // 2-bit labels: point i at byte i/4, bits 2(i%4); 16 points per dword
+      unsigned lv = (unsigned)lab << (2 * (lane & 15));
+      lv |= (unsigned)__shfl_xor((int)lv, 1);
+      lv |= (unsigned)__shfl_xor((int)lv, 2);
+      lv |= (unsigned)__shfl_xor((int)lv, 4);
+      lv |= (unsigned)__shfl_xor((int)lv, 8);
+      if ((lane & 15) == 0)
+        *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)b + 4 * (lane >> 4)) = lv;
+      unsigned long long rsign;
+      int rfirst;
+      bool rover = false;
+      const int wr = encode_block<kMaxWRankBlk>(delta, lane, s_pr[lb], rsign, rfirst, rover);
+      if (lane == 0) {
+        s_wr[lb] = wr;
+        out[a.off[R2] + b] = (uint8_t)wr;
+        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = rsign;
+        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = rfirst;
+      }
+    } else if (lane == 0) {
+      s_wr[lb] = 0;
+    }
+  }
+  {
+    const bool nf = __ballot(nonfinite) != 0, qo = __ballot(qover || wover) != 0;
+    if (lane == 0 && (nf || qo)) atomicOr(&s_flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
+  }
+  __syncthreads();
+
+  // chunk: constant-block bitmaps, local prefix of widths, look-back
+  if (wv == 0) {
+    const int b = c * kB + lane;
+    const bool bv = b < a.nb;
+    const int wd = s_wd[lane], wr = s_wr[lane];
+    const unsigned long long cb = __ballot(bv && wd == 0), cr = __ballot(bv && wr == 0);
+    const int sd = wave_incl_scan(wd, lane), sr = wave_incl_scan(wr, lane);
+    s_pfd[lane + 1] = sd;
+    s_pfr[lane + 1] = sr;
+    if (lane == 0) {
+      s_pfd[0] = 0;
+      s_pfr[0] = 0;
+      *reinterpret_cast<unsigned long long*>(a.out + a.off[S1] + 8 * (size_t)c) = cb;
+      if (a.topo) *reinterpret_cast<unsigned long long*>(a.out + a.off[R1] + 8 * (size_t)c) = cr;
+    }
+    const unsigned long long totd = (unsigned)__builtin_amdgcn_readlane(sd, 63);
+    const unsigned long long totr = (unsigned)__builtin_amdgcn_readlane(sr, 63);
+    if (lane == 0) {
+      unsigned long long* lbw = reinterpret_cast<unsigned long long*>(a.ws + kRegionOff);
+      const unsigned long long agg = (totd << 31) | totr;
+      unsigned long long exd = 0, exr = 0;
+      if (c == 0) {
+        st_rel(&lbw[0], (2ull << 62) | agg);
+      } else {
+        st_rel(&lbw[c], (1ull << 62) | agg);
+        int j = c - 1;
+        unsigned spins = 0;
+        while (j >= 0) {
+          const unsigned long long wv2 = ld_acq(&lbw[j]);
+          const unsigned st = (unsigned)(wv2 >> 62);
+          if (st == 0) {
+            if (++spins > kSpinLimit) {
+              atomicOr(&ct->timeout, 1u);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          exd += (wv2 >> 31) & 0x7FFFFFFFull;
+          exr += wv2 & 0x7FFFFFFFull;
+          if (st == 2) break;
+          --j;
+        }
+        st_rel(&lbw[c], (2ull << 62) | ((exd + totd) << 31) | (exr + totr));
+      }
+      s_exd = exd;
+      s_exr = exr;
+      *reinterpret_cast<unsigned long long*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * exd;
+      if (a.topo) *reinterpret_cast<unsigned long long*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * exr;
+      if (c == a.nch - 1) {
+        ct->tot_data = exd + totd;
+        ct->tot_rank = exr + totr;
+      }
+      if (s_flags) atomicOr(&ct->cflags, s_flags);
+    }
+  }
+  __syncthreads();
+
+  // payload: this chunk's planes, contiguous, coalesced from LDS
+  {
+    const int totd = s_pfd[kB];
+    uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + s_exd;
+    for (int o = tid; o < totd; o += WAVES * 64) {
+      int lo = 0, hi = kB;  // find lb with s_pfd[lb] <= o < s_pfd[lb+1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pfd[mid] <= o) lo = mid; else hi = mid;
+      }
+      dst[o] = s_pd[lo][o - s_pfd[lo]];
+    }
+    if (a.topo) {
+      const int totr = s_pfr[kB];
+      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.ws + shared_off(a.ws_bytes)) + s_exr;
+      for (int o = tid; o < totr; o += WAVES * 64) {
+        int lo = 0, hi = kB;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pfr[mid] <= o) lo = mid; else hi = mid;
+        }
+        rdst[o] = s_pr[lo][o - s_pfr[lo]];
+      }
+    }
+  }
+  // the last chunk zeroes the alignment gaps between the fixed-size parts
+  if (c == a.nch - 1 && tid < 8 * (X2 + 1)) {
+    const int s = tid >> 3, k = tid & 7;
+    const uint64_t end = a.off[s] + a.len[s];
+    if (end + k < a.off[s + 1]) a.out[end + k] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: header, rank payload, status, reset.
+
+__device__ void put8(uint8_t* h, int off, uint64_t v) { memcpy(h + off, &v, 8); }
+__device__ void put4(uint8_t* h, int off, uint32_t v) { memcpy(h + off, &v, 4); }
+__device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); }
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+  __shared__ uint8_t hdr[kHdr];
+  __shared__ unsigned s_sa[4], s_sb[4];
+  Ctrl* ct = ctrl_of(a.ws);
+  const int tid = threadIdx.x;
+  const uint64_t td = ct->tot_data, tr = a.topo ? ct->tot_rank : 0;
+  const uint64_t off_r5 = a.off[S5] + 8 * td;
+  const uint64_t* stage = reinterpret_cast<const uint64_t*>(a.ws + shared_off(a.ws_bytes));
+  uint64_t* r5 = reinterpret_cast<uint64_t*>(a.out + off_r5);
+  const uint64_t gt = blockIdx.x * (uint64_t)blockDim.x + tid, gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t o = gt; o < tr; o += gs) r5[o] = stage[o];
+  // look-back words back to zero for the next call
+  unsigned long long* lbw = reinterpret_cast<unsigned long long*>(a.ws + kRegionOff);
+  for (uint64_t o = gt; o < (uint64_t)a.nch; o += gs) lbw[o] = 0;
+
+  if (blockIdx.x == 0) {
+    const unsigned flags = ct->cflags;
+    float vmin, vmax;
+    const double eps = bound_eps(ct, a.eb_mode, a.eb, vmin, vmax);
+    const float e = a.eb_mode == TOPOSZP_EB_REL ? round_down_f(eps) : a.e_abs;
+    int status = TOPOSZP_OK;
+    if (ct->timeout) status = TOPOSZP_E_DEVICE;
+    else if (flags & 1u) status = TOPOSZP_E_NONFINITE;
+    else if (flags & 6u) status = TOPOSZP_E_RANGE;
+    for (int k = tid; k < kHdr; k += blockDim.x) hdr[k] = 0;
+    __syncthreads();
+    uint64_t total = 0;
+    if (tid == 0) {
+      int k = 3;
+      float sigma = 0.5f;
+      int si = 0;
+      if (a.rbf_policy == 0 && td <= (uint64_t)a.nb) { k = 7; sigma = 1.0f; si = 2; }
+      else if (a.rbf_policy == 0 && td <= 3 * (uint64_t)a.nb) { k = 5; sigma = 0.75f; si = 1; }
+      uint64_t off[kNSeg], len[kNSeg];
+      total = seg_layout((uint64_t)a.nb, a.topo, td, tr, off, len);
+      hdr[0] = 'T'; hdr[1] = 'S'; hdr[2] = 'Z'; hdr[3] = '1';
+      put2(hdr, 4, 1);
+      hdr[6] = (uint8_t)a.g.ndim;
+      hdr[7] = (uint8_t)(a.topo ? 1 : 0);
+      for (int d = 0; d < 3; ++d) put8(hdr, 8 + 8 * d, a.dims[d]);
+      put8(hdr, 32, (uint64_t)a.g.n);
+      put8(hdr, 40, (uint64_t)a.nb);
+      put4(hdr, 48, kB);
+      hdr[52] = (uint8_t)a.eb_mode;
+      hdr[53] = (uint8_t)k;
+      put2(hdr, 54, (uint16_t)a.max_rounds);
+      uint64_t u;
+      memcpy(&u, &a.eb, 8); put8(hdr, 56, u);
+      memcpy(&u, &eps, 8); put8(hdr, 64, u);
+      uint32_t v;
+      memcpy(&v, &e, 4); put4(hdr, 72, v);
+      memcpy(&v, &vmin, 4); put4(hdr, 76, v);
+      memcpy(&v, &vmax, 4); put4(hdr, 80, v);
+      memcpy(&v, &sigma, 4); put4(hdr, 84, v);
+      for (int d2 = 0; d2 < 10; ++d2) { memcpy(&v, &a.wtab[si][d2], 4); put4(hdr, 88 + 4 * d2, v); }
+      put8(hdr, 128, total);
+      put8(hdr, 136, td);
+      put8(hdr, 144, tr);
+      put8(hdr, 152, (uint64_t)a.nch);
+      for (int s = 0; s < kNSeg; ++s) {
+        put8(hdr, 160 + 8 * s, off[s]);
+        put8(hdr, 264 + 8 * s, len[s]);
+      }
+      *a.status = status;
+      *a.out_size = status == TOPOSZP_OK ? total : 0;
+    }
+    __syncthreads();
+    // Adler-32 of bytes [0, 376): A = 1 + sum b_i, B = n + sum (n - i) b_i (mod 65521)
+    unsigned sa = 0, sb = 0;
+    for (int i = tid; i < kSummed; i += blockDim.x) {
+      sa += hdr[i];
+      sb += (unsigned)(kSummed - i) * hdr[i];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      sa += (unsigned)__shfl_xor((int)sa, o);
+      sb += (unsigned)__shfl_xor((int)sb, o);
+    }
+    if ((tid & 63) == 0) {
+      s_sa[tid >> 6] = sa;
+      s_sb[tid >> 6] = sb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t A = 1, B = kSummed;
+      for (int k = 0; k < (int)(blockDim.x / 64); ++k) {
+        A += s_sa[k];
+        B += s_sb[k];
+      }
+      A %= 65521u;
+      B %= 65521u;
+      put4(hdr, kSummed, (uint32_t)((B << 16) | A));
+    }
+    __syncthreads();
+    for (int k = tid; k < kHdr; k += blockDim.x) a.out[k] = hdr[k];
+  }
+
+  // the last workgroup to finish resets the control block
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned d = __hip_atomic_fetch_add(&ct->done_fin, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == gridDim.x - 1) {
+      ct->ticket = 0;
+      ct->vmin_u = 0xFFFFFFFFu;
+      ct->vmax_u = 0u;
+      ct->cflags = 0;
+      ct->timeout = 0;
+      ct->tot_data = 0;
+      ct->tot_rank = 0;
+      __threadfence();
+      ct->done_fin = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decompression.
+
+struct Hdr {
+  int ok, ndim, topo, scope, k, max_rounds;
+  uint64_t dims[3], n, nb, nch, total, wdata, wrank;
+  float e, w[10];
+  uint64_t off[kNSeg], len[kNSeg];
+};
+
+template <typename T>
+__device__ __forceinline__ T rd(const uint8_t* p, int off) {
+  T v;
+  memcpy(&v, p + off, sizeof(T));
+  return v;
+}
+
+// Header checks (one wave): checksum, field ranges and the segment table
+// against the layout rule.  Result in *h (LDS); h->ok = 0 corrupt,
+// -1 capacity, 1 good.
+__device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_cap, Hdr* h,
+                             int lane) {
+  bool good = in_size >= (uint64_t)kHdr;
+  unsigned sa = 0, sb = 0;
+  if (good) {
+    for (int i = lane; i < kSummed; i += 64) {
+      const unsigned b = in[i];
+      sa += b;
+      sb += (unsigned)(kSummed - i) * b;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sa += (unsigned)__shfl_xor((int)sa, o);
+    sb += (unsigned)__shfl_xor((int)sb, o);
+  }
+  if (lane != 0) return;
+  h->ok = 0;
+  if (!good) return;
+  const uint32_t adler = (uint32_t)((((uint64_t)kSummed + sb) % 65521u) << 16 | ((1ull + sa) % 65521u));
+  if (in[0] != 'T' || in[1] != 'S' || in[2] != 'Z' || in[3] != '1') return;
+  if (rd<uint16_t>(in, 4) != 1) return;
+  if (rd<uint32_t>(in, kSummed) != adler || rd<uint32_t>(in, kSummed + 4) != 0) return;
+  h->ndim = in[6];
+  if (h->ndim != 2 && h->ndim != 3) return;
+  if (in[7] & ~3u) return;
+  h->topo = in[7] & 1;
+  h->scope = (in[7] >> 1) & 1;
+  uint64_t prod = 1;
+  for (int d = 0; d < 3; ++d) {
+    h->dims[d] = rd<uint64_t>(in, 8 + 8 * d);
+    if (h->dims[d] < 1 || h->dims[d] > (1ull << 31)) return;
+    if (d >= h->ndim && h->dims[d] != 1) return;
+    prod *= h->dims[d];
+    if (prod >= (1ull << 31)) return;
+  }
+  h->n = rd<uint64_t>(in, 32);
+  h->nb = rd<uint64_t>(in, 40);
+  h->nch = rd<uint64_t>(in, 152);
+  if (h->n != prod || h->nb != (h->n + kB - 1) / kB || h->nch != (h->nb + kB - 1) / kB) return;
+  if (rd<uint32_t>(in, 48) != (uint32_t)kB) return;
+  h->k = in[53];
+  h->max_rounds = rd<uint16_t>(in, 54);
+  if (in[52] > 1 || (h->k != 3 && h->k != 5 && h->k != 7) || h->max_rounds < 1) return;
+  h->e = rd<float>(in, 72);
+  if (!(h->e >= 0x1p-100f) || !(h->e <= 0x1p100f)) return;
+  for (int d2 = 0; d2 < 10; ++d2) {
+    h->w[d2] = rd<float>(in, 88 + 4 * d2);
+    if (!(h->w[d2] > 0.0f) || !(h->w[d2] <= 1.0f)) return;
+  }
+  h->total = rd<uint64_t>(in, 128);
+  h->wdata = rd<uint64_t>(in, 136);
+  h->wrank = rd<uint64_t>(in, 144);
+  if (h->wdata > h->nb * kMaxWData || h->wrank > h->nb * kMaxWRankAny) return;
+  uint64_t off[kNSeg], len[kNSeg];
+  const uint64_t total = seg_layout(h->nb, h->topo, h->wdata, h->wrank, off, len);
+  if (total != h->total || total > in_size) return;
+  for (int s = 0; s < kNSeg; ++s) {
+    h->off[s] = rd<uint64_t>(in, 160 + 8 * s);
+    h->len[s] = rd<uint64_t>(in, 264 + 8 * s);
+    if (h->off[s] != off[s] || h->len[s] != len[s]) return;
+  }
+  h->ok = (h->n <= out_cap) ? 1 : -1;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
+  constexpr int BPW = kB / WAVES;
+  __shared__ Hdr s_h;
+  __shared__ int s_pfd[kB + 1], s_pfr[kB + 1], s_wd[kB], s_wr[kB];
+  __shared__ unsigned long long s_xd, s_xr;
+  __shared__ int s_bad;
+  Ctrl* ct = ctrl_of(a.ws);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = blockIdx.x;
+  if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, lane);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const Hdr& h = s_h;
+  if (h.ok != 1) {
+    if (c == 0 && tid == 0) atomicOr(&ct->dflags, h.ok == -1 ? 2u : 1u);
+    return;
+  }
+  const int n = (int)h.n;
+  const int nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
+  const int ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
+  const int nz = h.ndim == 3 ? (int)h.dims[0] : 1;
+  const int ncol = h.ndim == 3 ? 7 : 5;
+  // the saddle queue lives in the workspace: idx u32[n], colour u8[n],
+  // pending f32[n], state u8[n]
+  const uint64_t qoff = shared_off(a.ws_bytes);
+  const uint64_t need = qoff + 10ull * (uint64_t)n + 64;
+  if (c == 0 && tid == 0) {
+    Plan& p = ct->plan;
+    p.valid = need <= a.ws_bytes;
+    p.topo = h.topo;
+    p.ndim = h.ndim;
+    p.k = h.k;
+    p.ncol = ncol;
+    p.max_rounds = h.max_rounds;
+    // one barrier per phase when no same-colour point can read another's
+    // update (window radius 1 in 3D, up to 2 in 2D); two otherwise
+    p.twostep = (h.ndim == 3) ? (h.k > 3) : (h.k > 5);
+    p.n = n;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    p.e = h.e;
+    for (int d2 = 0; d2 < 10; ++d2) p.w[d2] = h.w[d2];
+    p.s6_off = h.off[S6];
+    p.wl_cap = (uint64_t)n;
+    if (need > a.ws_bytes) atomicOr(&ct->dflags, 2u);
+  }
+  if ((uint64_t)c >= h.nch || need > a.ws_bytes) return;
+
+  // this chunk's widths, constant flags and payload offsets
+  if (wv == 0) {
+    const uint64_t b = (uint64_t)c * kB + lane;
+    const bool bv = b < h.nb;
+    const int wd = bv ? a.in[h.off[S2] + b] : 0;
+    const int wr = (bv && h.topo) ? a.in[h.off[R2] + b] : 0;
+    const unsigned long long cb = *reinterpret_cast<const unsigned long long*>(a.in + h.off[S1] + 8 * (uint64_t)c);
+    bool bad = bv && (wd > kMaxWData || (int)((cb >> lane) & 1) != (wd == 0));
+    if (h.topo) {
+      const unsigned long long cr = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R1] + 8 * (uint64_t)c);
+      bad |= bv && (wr > kMaxWRankAny || (int)((cr >> lane) & 1) != (wr == 0));
+    }
+    bad |= !bv && (((cb >> lane) & 1) != 0);
+    const int sd = wave_incl_scan(wd, lane), sr = wave_incl_scan(wr, lane);
+    s_pfd[lane + 1] = sd;
+    s_pfr[lane + 1] = sr;
+    s_wd[lane] = wd;
+    s_wr[lane] = wr;
+    const bool anybad = __ballot(bad) != 0;
+    if (lane == 0) {
+      s_pfd[0] = 0;
+      s_pfr[0] = 0;
+      const uint64_t totd = 8ull * (unsigned)__builtin_amdgcn_readlane(sd, 63);
+      const uint64_t totr = 8ull * (unsigned)__builtin_amdgcn_readlane(sr, 63);
+      const uint64_t xd = *reinterpret_cast<const uint64_t*>(a.in + h.off[X1] + 8 * (uint64_t)c);
+      const uint64_t nxd = (uint64_t)c + 1 < h.nch
+                               ? *reinterpret_cast<const uint64_t*>(a.in + h.off[X1] + 8 * ((uint64_t)c + 1))
+                               : h.len[S5];
+      bool b2 = anybad || (c == 0 && xd != 0) || xd > h.len[S5] || totd > h.len[S5] - xd || xd + totd != nxd;
+      uint64_t xr = 0;
+      if (h.topo) {
+        xr = *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * (uint64_t)c);
+        const uint64_t nxr = (uint64_t)c + 1 < h.nch
+                                 ? *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * ((uint64_t)c + 1))
+                                 : h.len[R5];
+        b2 = b2 || (c == 0 && xr != 0) || xr > h.len[R5] || totr > h.len[R5] - xr || xr + totr != nxr;
+      }
+      s_xd = xd;
+      s_xr = xr;
+      s_bad = b2 ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) atomicOr(&ct->dflags, 1u);
+    return;
+  }
+  const double ed = (double)h.e;
+  const float two_e = 2.0f * h.e;
+  const int dmax = h.scope ? n : kB;
+  unsigned* wl_idx = reinterpret_cast<unsigned*>(a.ws + qoff);
+  uint8_t* wl_col = a.ws + qoff + 4ull * n;
+  bool corrupt = false;
+  unsigned moves = 0, skips = 0;
+  for (int k = 0; k < BPW; ++k) {
+    const int lb = wv * BPW + k;
+    const uint64_t b = (uint64_t)c * kB + lb;
+    if (b >= h.nb) continue;
+    const int i = (int)(b * kB) + lane;
+    const bool valid = i < n;
+    const int first = *reinterpret_cast<const int*>(a.in + h.off[S4] + 4 * b);
+    const unsigned long long sign = *reinterpret_cast<const unsigned long long*>(a.in + h.off[S3] + 8 * b);
+    const int q = decode_block(a.in + h.off[S5] + s_xd + 8ull * s_pfd[lb], s_wd[lb], first, sign, lane);
+    corrupt |= valid && (q > kQMax || q < -kQMax);
+    const float rq = (float)q * two_e;  // float(2q) * e: the same exact product
+    float v = rq;
+    bool queue = false;
+    if (h.topo) {
+      const int rfirst = *reinterpret_cast<const int*>(a.in + h.off[R4] + 4 * b);
+      const unsigned long long rsign = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R3] + 8 * b);
+      const int dl = decode_block(a.in + h.off[R5] + s_xr + 8ull * s_pfr[lb], s_wr[lb], rfirst, rsign, lane);
+      corrupt |= valid && (dl < 0 || dl > dmax);
+      const unsigned lw = valid ? *reinterpret_cast<const unsigned*>(a.in + h.off[S6] + 16 * b + 4 * (lane >> 4)) : 0u;
+      const int lab = (int)((lw >> (2 * (lane & 15))) & 3u);
+      if (valid && dl > 0 && (lab == CLS_MIN || lab == CLS_MAX)) {
+        // flattened extremum: its neighbour maximum (minimum) is its own bin
+        // centre, so the stencil value is delta float steps beyond it
+        const long long kk = (long long)fkey(rq) + (lab == CLS_MAX ? (long long)dl : -(long long)dl);
+        const float cand = key2f(kk);
+        if (fabs((double)cand - (double)rq) <= ed) {
+          v = cand;
+          ++moves;
+        } else {
+          ++skips;
+        }
+      }
+      queue = valid && dl > 0 && lab == CLS_SAD;
+    }
+    if (valid) a.out[i] = v;
+    const unsigned long long qm = __ballot(queue);
+    if (qm) {
+      const int lead = __ffsll((long long)qm) - 1;
+      unsigned base = 0;
+      if (lane == lead) base = atomicAdd(&ct->wl_count, (unsigned)__popcll(qm));
+      base = (unsigned)__builtin_amdgcn_readlane((int)base, lead);
+      if (queue) {
+        const unsigned pos = base + mbcnt(qm);
+        const long long x = i % nx, t = i / nx, y = t % ny, z = t / ny;
+        const int col = h.ndim == 3 ? (int)((x + 2 * y + 3 * z) % 7) : (int)((x + 2 * y) % 5);
+        if (pos < (unsigned)n) {
+          wl_idx[pos] = (unsigned)i;
+          wl_col[pos] = (uint8_t)col;
+        }
+      }
+    }
+  }
+  const bool cb = __ballot(corrupt) != 0;
+  if (cb && lane == 0) atomicOr(&ct->dflags, 1u);
+  // stats (one atomic per wave)
+  for (int o = 32; o >= 1; o >>= 1) {
+    moves += (unsigned)__shfl_xor((int)moves, o);
+    skips += (unsigned)__shfl_xor((int)skips, o);
+  }
+  if (lane == 0 && (moves | skips)) {
+    atomicAdd(&ct->st_moves, (unsigned long long)moves);
+    atomicAdd(&ct->st_skips, (unsigned long long)skips);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Saddle refinement.
+
+__device__ int classify_at(const float* fld, int i, int pi, float pv, const Plan& p) {
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int x = i % nx, t = i / nx, y = t % ny, z = t / ny;
+  const int nxy = nx * ny;
+  float nb[6];
+  bool av[6];
+  av[0] = x > 0;
+  av[1] = x < nx - 1;
+  av[2] = y > 0;
+  av[3] = y < ny - 1;
+  av[4] = z > 0;
+  av[5] = z < nz - 1;
+  const int nbi[6] = {i - 1, i + 1, i - nx, i + nx, i - nxy, i + nxy};
+#pragma unroll
+  for (int j = 0; j < 6; ++j) nb[j] = av[j] ? (nbi[j] == pi ? pv : fld[nbi[j]]) : 0.0f;
+  const bool deg[3] = {nx < 2, ny < 2, nz < 2};
+  const float a = (i == pi) ? pv : fld[i];
+  return classify6(a, nb, av, deg);
+}
+
+// Candidate for a flattened saddle p and the acceptance tests:
+// 0 reject, 1 already a saddle, 2 accept (value in *vout).
+__device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Plan& pl, float* vout) {
+  if (classify_at(fld, p, -1, 0.0f, pl) == CLS_SAD) return 1;
+  const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+  const int x = p % nx, t = p / nx, y = t % ny, z = t / ny;
+  const int r = pl.k / 2, rz = pl.ndim == 3 ? r : 0;
+  double num = 0.0, den = 0.0;
+  for (int dz = -rz; dz <= rz; ++dz)
+    for (int dy = -r; dy <= r; ++dy)
+      for (int dx = -r; dx <= r; ++dx) {
+        const int d2 = dz * dz + dy * dy + dx * dx;
+        if (d2 == 0 || d2 > r * r) continue;
+        const int zz = z + dz, yy = y + dy, xx = x + dx;
+        if (zz < 0 || zz >= nz || yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
+        const double wt = (double)pl.w[d2];
+        num = num + wt * (double)fld[(zz * ny + yy) * nx + xx];
+        den = den + wt;
+      }
+  if (den == 0.0) return 0;
+  const float v = (float)(num / den);
+  if (!(fabs((double)v - (double)fld[p]) <= (double)pl.e)) return 0;
+  if (classify_at(fld, p, p, v, pl) != CLS_SAD) return 0;
+  const int nxy = nx * ny;
+  const int nbi[6] = {p - 1, p + 1, p - nx, p + nx, p - nxy, p + nxy};
+  const bool av[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < nz - 1};
+  for (int j = 0; j < 6; ++j) {
+    if (!av[j]) continue;
+    const int q = nbi[j];
+    const int before = classify_at(fld, q, -1, 0.0f, pl);
+    const int after = classify_at(fld, q, p, v, pl);
+    const int lab = (labels[q >> 2] >> (2 * (q & 3))) & 3;
+    if (after != before && !(before == CLS_R && after == lab)) return 0;
+  }
+  *vout = v;
+  return 2;
+}
+
+__device__ __forceinline__ void grid_sync(Ctrl* ct, bool single, unsigned& epoch) {
+  __threadfence();
+  __syncthreads();
+  if (single) return;
+  if (threadIdx.x == 0) {
+    ++epoch;
+    const unsigned target = epoch * gridDim.x;
+    __hip_atomic_fetch_add(&ct->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(&ct->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kSpinLimit) {
+        atomicOr(&ct->timeout, 2u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void refine_kernel(RefArgs a) {
+  __shared__ Plan s_p;
+  __shared__ unsigned s_count, s_flags;
+  Ctrl* ct = ctrl_of(a.ws);
+  if (threadIdx.x == 0) {
+    s_p = ct->plan;
+    s_count = ct->wl_count;
+    s_flags = ct->dflags;
+  }
+  __syncthreads();
+  const Plan& pl = s_p;
+  const unsigned count = pl.valid && s_count > (unsigned)pl.n ? (unsigned)pl.n : s_count;
+  const bool ok = s_flags == 0 && pl.valid && pl.topo;
+  const bool single = count <= (unsigned)kSingleMax;
+  const bool part = ok && count > 0 && (!single || blockIdx.x == 0);
+  unsigned* rc = reinterpret_cast<unsigned*>(a.ws + kRcOff);
+  if (part) {
+    const uint64_t qoff = shared_off(a.ws_bytes);
+    const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + qoff);
+    const uint8_t* col = a.ws + qoff + 4ull * pl.n;
+    float* pend = reinterpret_cast<float*>(a.ws + qoff + ((5ull * pl.n + 3) & ~3ull));
+    uint8_t* state = reinterpret_cast<uint8_t*>(pend + pl.n);
+    const uint8_t* labels = a.in + pl.s6_off;
+    const unsigned nthr = single ? blockDim.x : gridDim.x * blockDim.x;
+    const unsigned gtid = single ? threadIdx.x : blockIdx.x * blockDim.x + threadIdx.x;
+    for (unsigned t = gtid; t < count; t += nthr) state[t] = 0;
+    unsigned epoch = 0;
+    grid_sync(ct, single, epoch);
+    int round = 1;
+    for (; round <= pl.max_rounds; ++round) {
+      for (int cc = 0; cc < pl.ncol; ++cc) {
+        for (unsigned t = gtid; t < count; t += nthr) {
+          if (state[t] || col[t] != cc) continue;
+          const int p = (int)idx[t];
+          float v;
+          const int res = evaluate(a.out, labels, p, pl, &v);
+          if (res == 1) {
+            state[t] = 1;
+          } else if (res == 2) {
+            if (pl.twostep) {
+              pend[t] = v;
+              state[t] = 2;
+            } else {
+              a.out[p] = v;
+              state[t] = 1;
+            }
+            atomicAdd(&rc[round], 1u);
+          }
+        }
+        grid_sync(ct, single, epoch);
+        if (pl.twostep) {
+          for (unsigned t = gtid; t < count; t += nthr)
+            if (state[t] == 2) {
+              a.out[idx[t]] = pend[t];
+              state[t] = 1;
+            }
+          grid_sync(ct, single, epoch);
+        }
+      }
+      const unsigned commits = __hip_atomic_load(&rc[round], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (commits == 0) break;
+    }
+    if (gtid == 0) ct->rounds_used = (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
+  }
+  // the last workgroup to finish records stats and status and resets
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned d = __hip_atomic_fetch_add(&ct->done_ref, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == gridDim.x - 1) {
+      __threadfence();
+      const unsigned ru = (ok && count > 0) ? ct->rounds_used : 0;
+      unsigned long long commits = 0;
+      for (unsigned r = 1; r <= ru; ++r) {
+        commits += rc[r];
+        rc[r] = 0;
+      }
+      const unsigned fl = ct->dflags;
+      ct->stats[0] = ru;
+      ct->stats[1] = commits;
+      ct->stats[2] = count;
+      ct->stats[3] = ct->st_moves;
+      ct->stats[4] = ct->st_skips;
+      *a.status = ct->timeout ? TOPOSZP_E_DEVICE
+                  : (fl & 1u) ? TOPOSZP_E_CORRUPT : ((fl & 2u) ? TOPOSZP_E_CAPACITY : TOPOSZP_OK);
+      ct->timeout = 0;
+      ct->dflags = 0;
+      ct->wl_count = 0;
+      ct->bar = 0;
+      ct->rounds_used = 0;
+      ct->st_moves = 0;
+      ct->st_skips = 0;
+      ct->plan.valid = 0;
+      __threadfence();
+      ct->done_ref = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+struct HostGeom {
+  Geom g;
+  uint64_t dims[3];
+  uint64_t nb, nch;
+};
+
+int host_geom(uint32_t ndim, const uint64_t* dims, HostGeom* hg) {
+  if (!dims || (ndim != 2 && ndim != 3)) return TOPOSZP_E_INVALID_ARG;
+  uint64_t n = 1;
+  for (uint32_t d = 0; d < ndim; ++d) {
+    if (dims[d] < 1) return TOPOSZP_E_INVALID_ARG;
+    if (dims[d] > (1ull << 31)) return TOPOSZP_E_UNSUPPORTED;
+    n *= dims[d];
+    if (n >= (1ull << 31)) return TOPOSZP_E_UNSUPPORTED;
+  }
+  hg->dims[0] = dims[0];
+  hg->dims[1] = dims[1];
+  hg->dims[2] = ndim == 3 ? dims[2] : 1;
+  hg->g.ndim = (int)ndim;
+  hg->g.n = (int)n;
+  hg->g.nx = (int)(ndim == 3 ? dims[2] : dims[1]);
+  hg->g.ny = (int)(ndim == 3 ? dims[1] : dims[0]);
+  hg->g.nz = (int)(ndim == 3 ? dims[0] : 1);
+  hg->nb = (n + kB - 1) / kB;
+  hg->nch = (hg->nb + kB - 1) / kB;
+  return TOPOSZP_OK;
+}
+
+size_t ws_need(const HostGeom& hg) {
+  // queue (10 N) or rank staging (56 per block), plus the look-back area
+  const uint64_t stage = 8ull * kMaxWRankBlk * hg.nb, queue = 10ull * (uint64_t)hg.g.n + 64;
+  uint64_t w = kRegionOff + (stage > queue ? stage : queue) + 4096;
+  w += lookback_bytes(2 * w);
+  return (size_t)(w + 255) & ~size_t(255);
+}
+
+float host_round_down(double d) {
+  float f = (float)d;
+  if ((double)f > d) f = nextafterf(f, 0.0f);
+  return f;
+}
+
+// timing
+bool g_timing = false;
+hipEvent_t g_ev[6][2];
+bool g_ev_used[6];
+bool g_ev_init = false;
+int g_coop_grid = 0;
+
+void ev_begin(int k, hipStream_t s) {
+  if (!g_timing) return;
+  if (!g_ev_init) {
+    for (int i = 0; i < 6; ++i) {
+      (void)hipEventCreate(&g_ev[i][0]);
+      (void)hipEventCreate(&g_ev[i][1]);
+    }
+    g_ev_init = true;
+  }
+  (void)hipEventRecord(g_ev[k][0], s);
+}
+void ev_end(int k, hipStream_t s) {
+  if (!g_timing) return;
+  (void)hipEventRecord(g_ev[k][1], s);
+  g_ev_used[k] = true;
+}
+
+constexpr int kEncWaves = 4;
+constexpr int kDecWaves = 4;
+
+}  // namespace
+
+extern "C" {
+
+int toposzp_version(void) { return 1; }
+
+const char* toposzp_strerror(int status) {
+  switch (status) {
+    case TOPOSZP_OK: return "ok";
+    case TOPOSZP_E_INVALID_ARG: return "invalid argument";
+    case TOPOSZP_E_NONFINITE: return "non-finite value in the input field";
+    case TOPOSZP_E_RANGE: return "error bound or values outside the quantizer range";
+    case TOPOSZP_E_CAPACITY: return "output or workspace buffer too small";
+    case TOPOSZP_E_CORRUPT: return "corrupt compressed stream";
+    case TOPOSZP_E_DEVICE: return "HIP runtime error";
+    case TOPOSZP_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+size_t toposzp_compress_bound(uint32_t ndim, const uint64_t* dims) {
+  HostGeom hg;
+  if (host_geom(ndim, dims, &hg) != TOPOSZP_OK) return 0;
+  uint64_t off[kNSeg], len[kNSeg];
+  return (size_t)seg_layout(hg.nb, 1, hg.nb * kMaxWData, hg.nb * kMaxWRankBlk, off, len);
+}
+
+size_t toposzp_workspace_size(uint32_t ndim, const uint64_t* dims) {
+  HostGeom hg;
+  if (host_geom(ndim, dims, &hg) != TOPOSZP_OK) return 0;
+  return ws_need(hg);
+}
+
+int toposzp_workspace_init(void* d_ws, size_t ws_bytes, void* stream) {
+  if (!d_ws || ws_bytes < kRegionOff || ((uintptr_t)d_ws & 255)) return TOPOSZP_E_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t n8 = ws_bytes / 8;
+  unsigned grid = (unsigned)((n8 + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(ws_init_kernel, dim3(grid), dim3(256), 0, s, (uint8_t*)d_ws, (uint64_t)ws_bytes);
+  hipLaunchKernelGGL(ws_init_keys_kernel, dim3(1), dim3(1), 0, s, (uint8_t*)d_ws);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode,
+                     double eb, const toposzp_params* params, void* d_ws, size_t ws_bytes,
+                     uint8_t* d_out, size_t out_cap, uint64_t* d_out_size, int32_t* d_status,
+                     void* stream) {
+  toposzp_params p = {64, 0, 0, 16, 1};
+  if (params) p = *params;
+  HostGeom hg;
+  int rc = host_geom(ndim, dims, &hg);
+  if (rc != TOPOSZP_OK) return rc;
+  if (!d_field || !d_ws || !d_out || !d_out_size || !d_status) return TOPOSZP_E_INVALID_ARG;
+  if (((uintptr_t)d_field & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_out & 7) ||
+      ((uintptr_t)d_out_size & 7) || ((uintptr_t)d_status & 3))
+    return TOPOSZP_E_INVALID_ARG;
+  if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != TOPOSZP_EB_ABS && eb_mode != TOPOSZP_EB_REL))
+    return TOPOSZP_E_INVALID_ARG;
+  if (p.block != (uint32_t)kB || (p.topo != 0 && p.topo != 1) || (p.rank_scope != 0 && p.rank_scope != 1) ||
+      (p.rbf_policy != 0 && p.rbf_policy != 1) || p.max_rounds < 1 || p.max_rounds > kMaxRounds)
+    return TOPOSZP_E_INVALID_ARG;
+  if (p.rank_scope == 1 && p.topo) return TOPOSZP_E_UNSUPPORTED;
+  if (out_cap < toposzp_compress_bound(ndim, dims)) return TOPOSZP_E_CAPACITY;
+  if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+
+  EncArgs ea;
+  ea.f = d_field;
+  ea.out = d_out;
+  ea.ws = (uint8_t*)d_ws;
+  ea.ws_bytes = ws_bytes;
+  ea.g = hg.g;
+  ea.nb = (int)hg.nb;
+  ea.nch = (int)hg.nch;
+  ea.topo = p.topo;
+  ea.eb_mode = eb_mode;
+  ea.rbf_policy = p.rbf_policy;
+  ea.max_rounds = p.max_rounds;
+  ea.eb = eb;
+  ea.e_abs = host_round_down(eb);
+  seg_layout(hg.nb, p.topo, 0, 0, ea.off, ea.len);
+
+  FinArgs fa;
+  fa.out = d_out;
+  fa.ws = (uint8_t*)d_ws;
+  fa.ws_bytes = ws_bytes;
+  fa.out_size = d_out_size;
+  fa.status = d_status;
+  fa.g = hg.g;
+  for (int d = 0; d < 3; ++d) fa.dims[d] = hg.dims[d];
+  fa.nb = ea.nb;
+  fa.nch = ea.nch;
+  fa.topo = p.topo;
+  fa.eb_mode = eb_mode;
+  fa.rbf_policy = p.rbf_policy;
+  fa.max_rounds = p.max_rounds;
+  fa.eb = eb;
+  fa.e_abs = ea.e_abs;
+  memcpy(fa.off, ea.off, sizeof(ea.off));
+  memcpy(fa.len, ea.len, sizeof(ea.len));
+  const double sig[3] = {0.5, 0.75, 1.0};
+  for (int t = 0; t < 3; ++t)
+    for (int d2 = 0; d2 < 10; ++d2) fa.wtab[t][d2] = (float)exp(-(double)d2 / (2.0 * sig[t] * sig[t]));
+
+  for (int k = 0; k < 3; ++k) g_ev_used[k] = false;
+  if (eb_mode == TOPOSZP_EB_REL) {
+    unsigned grid = (unsigned)((hg.g.n / 4 + 255) / 256);
+    if (grid > 2048) grid = 2048;
+    if (grid < 1) grid = 1;
+    ev_begin(0, s);
+    hipLaunchKernelGGL(range_kernel, dim3(grid), dim3(256), 0, s, d_field, hg.g.n, (uint8_t*)d_ws);
+    ev_end(0, s);
+  }
+  ev_begin(1, s);
+  hipLaunchKernelGGL(encode_kernel<kEncWaves>, dim3(ea.nch), dim3(kEncWaves * 64), 0, s, ea);
+  ev_end(1, s);
+  unsigned fgrid = (unsigned)((kMaxWRankBlk * hg.nb + 255) / 256);
+  if (fgrid > 1024) fgrid = 1024;
+  if (fgrid < 1) fgrid = 1;
+  ev_begin(2, s);
+  hipLaunchKernelGGL(finalize_kernel, dim3(fgrid), dim3(256), 0, s, fa);
+  ev_end(2, s);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_elems,
+                       void* d_ws, size_t ws_bytes, int32_t* d_status, void* stream) {
+  if (!d_in || !d_out || !d_ws || !d_status || out_cap_elems < 1) return TOPOSZP_E_INVALID_ARG;
+  if (((uintptr_t)d_in & 7) || ((uintptr_t)d_out & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_status & 3))
+    return TOPOSZP_E_INVALID_ARG;
+  if (ws_bytes < kRegionOff + 64) return TOPOSZP_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t cap = out_cap_elems;
+  if (cap > (1ull << 31)) cap = (1ull << 31);
+  const uint64_t nch = ((cap + kB - 1) / kB + kB - 1) / kB;
+  DecArgs da;
+  da.in = d_in;
+  da.in_size = in_size;
+  da.out = d_out;
+  da.out_cap = out_cap_elems;
+  da.ws = (uint8_t*)d_ws;
+  da.ws_bytes = ws_bytes;
+  for (int k = 3; k < 5; ++k) g_ev_used[k] = false;
+  ev_begin(3, s);
+  hipLaunchKernelGGL(decode_kernel<kDecWaves>, dim3((unsigned)nch), dim3(kDecWaves * 64), 0, s, da);
+  ev_end(3, s);
+  if (g_coop_grid == 0) {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, refine_kernel, 256, 0) != hipSuccess)
+      return TOPOSZP_E_DEVICE;
+    int g = per * cus;
+    if (g > cus) g = cus;
+    if (g < 1) g = 1;
+    g_coop_grid = g;
+  }
+  RefArgs ra;
+  ra.in = d_in;
+  ra.out = d_out;
+  ra.ws = (uint8_t*)d_ws;
+  ra.ws_bytes = ws_bytes;
+  ra.status = d_status;
+  void* args[] = {&ra};
+  ev_begin(4, s);
+  hipError_t err = hipLaunchCooperativeKernel((const void*)refine_kernel, dim3(g_coop_grid), dim3(256),
+                                              args, 0, s);
+  ev_end(4, s);
+  if (err != hipSuccess) return TOPOSZP_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_compress_sync(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode,
+                          double eb, const toposzp_params* params, void* d_ws, size_t ws_bytes,
+                          uint8_t* d_out, size_t out_cap, uint64_t* h_out_size, void* stream) {
+  // status and size travel through the tail of the workspace's control block
+  uint8_t* ws = (uint8_t*)d_ws;
+  if (!ws || ws_bytes < kRegionOff) return TOPOSZP_E_INVALID_ARG;
+  uint64_t* d_size = reinterpret_cast<uint64_t*>(ws + kCtrlBytes - 16);
+  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kCtrlBytes - 8);
+  int rc = toposzp_compress(d_field, ndim, dims, eb_mode, eb, params, d_ws, ws_bytes, d_out, out_cap,
+                            d_size, d_stat, stream);
+  if (rc != TOPOSZP_OK) return rc;
+  uint64_t sz = 0;
+  int32_t st = 0;
+  if (hipMemcpyAsync(&sz, d_size, 8, hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipMemcpyAsync(&st, d_stat, 4, hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return TOPOSZP_E_DEVICE;
+  if (h_out_size) *h_out_size = sz;
+  return st;
+}
+
+int toposzp_decompress_sync(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_elems,
+                            void* d_ws, size_t ws_bytes, void* stream) {
+  uint8_t* ws = (uint8_t*)d_ws;
+  if (!ws || ws_bytes < kRegionOff) return TOPOSZP_E_INVALID_ARG;
+  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kCtrlBytes - 8);
+  int rc = toposzp_decompress(d_in, in_size, d_out, out_cap_elems, d_ws, ws_bytes, d_stat, stream);
+  if (rc != TOPOSZP_OK) return rc;
+  int32_t st = 0;
+  if (hipMemcpyAsync(&st, d_stat, 4, hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return TOPOSZP_E_DEVICE;
+  return st;
+}
+
+int toposzp_inspect(const uint8_t* h, size_t n, toposzp_info* out) {
+  if (!h || !out) return TOPOSZP_E_INVALID_ARG;
+  if (n < (size_t)kHdr) return TOPOSZP_E_CORRUPT;
+  uint32_t A = 1, B = 0;
+  for (int i = 0; i < kSummed; ++i) {
+    A = (A + h[i]) % 65521u;
+    B = (B + A) % 65521u;
+  }
+  uint32_t stored, pad;
+  memcpy(&stored, h + kSummed, 4);
+  memcpy(&pad, h + kSummed + 4, 4);
+  if (memcmp(h, "TSZ1", 4) != 0 || stored != ((B << 16) | A) || pad != 0) return TOPOSZP_E_CORRUPT;
+  uint16_t ver, mr;
+  memcpy(&ver, h + 4, 2);
+  if (ver != 1) return TOPOSZP_E_CORRUPT;
+  memset(out, 0, sizeof(*out));
+  out->ndim = h[6];
+  out->topo = h[7] & 1;
+  out->rank_scope = (h[7] >> 1) & 1;
+  out->eb_mode = h[52];
+  out->k_size = h[53];
+  memcpy(&mr, h + 54, 2);
+  out->max_rounds = mr;
+  memcpy(out->dims, h + 8, 24);
+  memcpy(&out->n, h + 32, 8);
+  memcpy(&out->nblocks, h + 40, 8);
+  memcpy(&out->eb, h + 56, 8);
+  memcpy(&out->eps, h + 64, 8);
+  memcpy(&out->e, h + 72, 4);
+  memcpy(&out->vmin, h + 76, 4);
+  memcpy(&out->vmax, h + 80, 4);
+  memcpy(&out->sigma, h + 84, 4);
+  memcpy(&out->total_bytes, h + 128, 8);
+  memcpy(&out->data_planes, h + 136, 8);
+  memcpy(&out->rank_planes, h + 144, 8);
+  if (out->ndim != 2 && out->ndim != 3) return TOPOSZP_E_CORRUPT;
+  return TOPOSZP_OK;
+}
+
+int toposzp_decompress_stats(const void* d_ws, int64_t out[5], void* stream) {
+  if (!d_ws || !out) return TOPOSZP_E_INVALID_ARG;
+  const Ctrl* ct = (const Ctrl*)d_ws;
+  unsigned long long st[5];
+  if (hipMemcpyAsync(st, (const void*)ct->stats, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
+          hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return TOPOSZP_E_DEVICE;
+  for (int k = 0; k < 5; ++k) out[k] = (int64_t)st[k];
+  return TOPOSZP_OK;
+}
+
+int toposzp_set_timing(int enable) {
+  g_timing = enable != 0;
+  return TOPOSZP_OK;
+}
+
+int toposzp_kernel_times(float* ms, int max) {
+  if (!ms) return 0;
+  int k = 0;
+  for (; k < 5 && k < max; ++k) {
+    ms[k] = -1.0f;
+    if (g_ev_init && g_ev_used[k]) {
+      float t = -1.0f;
+      if (hipEventElapsedTime(&t, g_ev[k][0], g_ev[k][1]) == hipSuccess) ms[k] = t;
+    }
+  }
+  return k;
+}
+
+}  // extern "C"

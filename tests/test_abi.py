@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every call include/toposzp.h declares;
+host-side parts (bounds, workspace sizes, argument checks, header parsing)
+agree with the format and the oracle.  No GPU work is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "toposzp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(toposzp_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def tsz():
+    import paper_2602_17552_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def test_exports_every_declared_symbol(tsz):
+    names = _declared()
+    assert len(names) >= 13
+    for nm in names:
+        assert hasattr(tsz.lib(), nm), nm
+    assert sorted(tsz.SYMBOLS) == names
+
+
+def test_version_and_messages(tsz):
+    assert tsz.lib().toposzp_version() == 1
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
+        assert tsz.strerror(code) != "unknown status"
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (512, 512), (1800, 3600), (256, 256, 256), (7, 9, 11),
+                                   (1, 4097)])
+def test_bound_matches_oracle_and_format(tsz, ora, shape):
+    d = np.ones(3, np.uint64)
+    d[: len(shape)] = shape
+    assert tsz.compress_bound(shape) == ora.lib().ora_compress_bound(len(shape), d, 0)
+    n = int(np.prod(shape))
+    assert tsz.workspace_size(shape) >= 10 * n
+
+
+def test_invalid_arguments_rejected_on_host(tsz):
+    L = tsz.lib()
+    dims = (C.c_uint64 * 3)(4, 4, 1)
+    p = tsz.Params(64, 0, 0, 16, 1)
+    fake = C.c_void_p(4096)
+    args = lambda nd, eb, mode, par: L.toposzp_compress(fake, nd, dims, mode, eb, C.byref(par), fake,
+                                                        1 << 30, fake, 1 << 30, fake, fake, None)
+    assert args(4, 0.1, 0, p) == tsz.E_INVALID_ARG
+    assert args(2, 0.0, 0, p) == tsz.E_INVALID_ARG
+    assert args(2, float("nan"), 0, p) == tsz.E_INVALID_ARG
+    assert args(2, 0.1, 7, p) == tsz.E_INVALID_ARG
+    assert args(2, 0.1, 0, tsz.Params(32, 0, 0, 16, 1)) == tsz.E_INVALID_ARG
+    assert args(2, 0.1, 0, tsz.Params(64, 0, 0, 0, 1)) == tsz.E_INVALID_ARG
+    assert args(2, 0.1, 0, tsz.Params(64, 1, 0, 16, 1)) == tsz.E_UNSUPPORTED
+    big = (C.c_uint64 * 3)(1 << 16, 1 << 16, 1)
+    assert L.toposzp_compress(fake, 2, big, 0, 0.1, C.byref(p), fake, 1 << 30, fake, 1 << 30, fake,
+                              fake, None) == tsz.E_UNSUPPORTED
+    # too-small output or workspace
+    assert L.toposzp_compress(fake, 2, dims, 0, 0.1, C.byref(p), fake, 1 << 30, fake, 10, fake, fake,
+                              None) == tsz.E_CAPACITY
+    assert L.toposzp_compress(fake, 2, dims, 0, 0.1, C.byref(p), fake, 10, fake, 1 << 30, fake, fake,
+                              None) == tsz.E_CAPACITY
+    assert L.toposzp_decompress(None, 10, fake, 10, fake, 1 << 30, fake, None) == tsz.E_INVALID_ARG
+
+
+def test_inspect_oracle_stream(tsz, ora):
+    from paper_2602_17552_amd import datagen
+    f = datagen.gaussian_bumps_2d(40, 70, 5, seed=2)
+    rc, s = ora.compress(f, 1e-3, "rel")
+    rc, info = tsz.inspect(bytes(s[:512]))
+    assert rc == tsz.OK
+    rc, oi = ora.inspect(s)
+    assert info["dims"] == [40, 70, 1] and info["n"] == f.size
+    assert info["total_bytes"] == s.size and info["k_size"] == oi["k"]
+    assert info["data_planes"] == oi["wdata"] and info["rank_planes"] == oi["wrank"]
+    assert np.float32(info["e"]) == np.float32(oi["e"])
+    bad = bytearray(bytes(s[:512]))
+    bad[20] ^= 1
+    assert tsz.inspect(bytes(bad))[0] == tsz.E_CORRUPT
