@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""TopoSZp throughput on one MI355X.
+
+A step is one pass of the whole path over one field: compression (range pass,
+encode, finalize) followed by decompression of that stream (decode with the
+extrema stencil, saddle refinement rounds).  The workload is the 1800 x 3600
+float32 climate-grid field (64 random plane waves + N(0, 1e-2^2) noise, seed 1)
+at relative error bound 1e-3.  Fields, streams and outputs stay resident in
+HBM; the timed loop rotates over enough copies (> 256 MB) that the inputs are
+not served from the 256 MB Infinity Cache between steps.
+
+Prints one JSON line: value = field bytes per second through a full round
+trip; compress and decompress GB/s from their own timed loops; the roofline of
+the dominant kernel from HIP events recorded around each kernel on the call's
+stream; and the CPU oracle timed on the host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+SHAPE = (1800, 3600)
+EB = 1e-3
+WORKLOAD = "1800x3600 float32 climate-grid field (64 plane waves |k|^-1.5 + N(0,1e-2^2) noise, seed 1), relative bound 1e-3"
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2602_17552_amd", "csrc", "toposzp.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(kernel, per_launch_alg):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_1800x3600_rel1e-3.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != _src_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(field, eb, target_s=10.0):
+    """The oracle (single-threaded C) on whole-field round trips, repeated
+    until about target_s of CPU time has been spent."""
+    from oracle import oracle as ora
+    ora.lib()
+    t0 = time.perf_counter()
+    reps = 0
+    tc = td = 0.0
+    while True:
+        a = time.perf_counter()
+        rc, s = ora.compress(field, eb, "rel")
+        b = time.perf_counter()
+        rc2, rec, _ = ora.decompress(s, field.shape)
+        c = time.perf_counter()
+        assert rc == 0 and rc2 == 0
+        tc += b - a
+        td += c - b
+        reps += 1
+        if c - t0 >= target_s:
+            break
+    nbytes = field.nbytes
+    return {
+        "value": round(nbytes * reps / (tc + td) / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "%d whole-field round trips (compress + decompress) of the workload; "
+                  "compress %.4f GB/s, decompress %.4f GB/s" % (reps, nbytes * reps / tc / 1e9,
+                                                                  nbytes * reps / td / 1e9),
+    }, s, rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--copies", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--probe", action="store_true",
+                    help="a few steps only (for profiler runs), no JSON line")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_17552_amd as tsz
+    from paper_2602_17552_amd import datagen
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    field = datagen.cfg1()
+    n = field.size
+    nbytes = field.nbytes
+    R = max(1, args.copies)
+    base = torch.from_numpy(field).to(dev)
+    ins = [base.clone() for _ in range(R)]
+    cap = tsz.compress_bound(SHAPE)
+    outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(R)]
+    recs = [torch.empty(SHAPE, dtype=torch.float32, device=dev) for _ in range(R)]
+    sizes = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(R)]
+    cst = torch.zeros(1, dtype=torch.int32, device=dev)
+    dst = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = tsz.Workspace(SHAPE, dev)
+    stream = torch.cuda.current_stream()
+
+    def comp(k):
+        tsz.compress_async(ins[k], EB, "rel", ws=ws, out=outs[k], size=sizes[k], status=cst)
+
+    # every copy compressed once so each has a stream of known size
+    for k in range(R):
+        comp(k)
+    torch.cuda.synchronize()
+    assert int(cst.item()) == 0, tsz.strerror(int(cst.item()))
+    slen = [int(s.item()) for s in sizes]
+
+    def decomp(k):
+        tsz.decompress_async(outs[k], slen[k], recs[k], ws=ws, status=dst)
+
+    def step(k):
+        comp(k)
+        decomp(k)
+
+    if args.probe:
+        for i in range(6):
+            step(i % R)
+        torch.cuda.synchronize()
+        ok = int(cst.item()) == 0 and int(dst.item()) == 0
+        print("probe steps done, status ok:", ok, flush=True)
+        # a plain copy of known size for counter calibration
+        big = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        big2 = torch.empty_like(big)
+        for _ in range(3):
+            big2.copy_(big)
+        torch.cuda.synchronize()
+        return
+
+    def timed(fn, steps, warm):
+        for i in range(warm):
+            fn(i % R)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            fn(i % R)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_wall0 = time.perf_counter()
+    ms_step = timed(step, args.steps, args.warmup)
+    t_wall = time.perf_counter() - t_wall0
+    assert int(cst.item()) == 0 and int(dst.item()) == 0
+    ms_comp = timed(comp, args.steps, args.warmup)
+    ms_dec = timed(decomp, args.steps, args.warmup)
+
+    # per-kernel durations: HIP events recorded by the library around each of
+    # its kernels, on the call's stream
+    tsz.set_timing(True)
+    names = ["range", "encode", "finalize", "decode", "refine"]
+    acc = {k: 0.0 for k in names}
+    kreps = min(args.steps, 40)
+    for i in range(kreps):
+        step(i % R)
+        torch.cuda.synchronize()
+        t = tsz.kernel_times()
+        for k in names:
+            acc[k] += max(t[k], 0.0)
+    tsz.set_timing(False)
+    kms = {k: acc[k] / kreps for k in names}
+
+    # parity of this workload's stream and reconstruction against the oracle,
+    # and its topology counts
+    s_gpu = outs[0][: slen[0]].cpu().numpy()
+    rec_gpu = recs[0].cpu().numpy()
+    stats = tsz.decompress_stats(ws)
+    if args.no_cpu:
+        cpu = None
+        parity = None
+        from oracle import oracle as ora
+        ev = ora.eval_topology(field, rec_gpu)
+    else:
+        cpu, s_ref, rec_ref = cpu_baseline(field, EB)
+        parity = bool(np.array_equal(s_gpu, s_ref) and
+                      np.array_equal(rec_gpu.view(np.uint32), rec_ref.view(np.uint32)))
+        from oracle import oracle as ora
+        ev = ora.eval_topology(field, rec_gpu)
+
+    S = slen[0]
+    # algorithmic bytes per launch: encode reads the field and writes the
+    # stream; decode reads the stream and writes the field
+    alg = {"encode": 4 * n + S, "decode": S + 4 * n, "range": 4 * n}
+    dom = max(["encode", "decode", "range"], key=lambda k: kms[k])
+    achieved = alg[dom] / (kms[dom] * 1e-3) / 1e9
+    kernels = {k: {"ms": round(kms[k], 5),
+                   "GBps": round(alg[k] / (kms[k] * 1e-3) / 1e9, 1) if k in alg and kms[k] > 0 else None}
+               for k in names}
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": _traffic(dom, alg[dom])}
+    value = nbytes / (ms_step * 1e-3) / 1e9
+    line = {
+        "metric": "compress/decompress GB/s at rel eb 1e-3; missed CPs; serve p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "shape": list(SHAPE), "eb": EB, "eb_mode": "rel",
+                   "field_bytes": nbytes, "copies_rotated": R},
+        "compress_gbps": round(nbytes / (ms_comp * 1e-3) / 1e9, 2),
+        "decompress_gbps": round(nbytes / (ms_dec * 1e-3) / 1e9, 2),
+        "compress_ms": round(ms_comp, 5),
+        "decompress_ms": round(ms_dec, 5),
+        "ratio": round(nbytes / S, 3),
+        "bits_per_value": round(8 * S / n, 3),
+        "missed_cps": {"FN": ev["FN"], "FP": ev["FP"], "FT": ev["FT"], "FN_saddle": ev["FN_sad"],
+                       "FN_extrema": ev["FN_min"] + ev["FN_max"]},
+        "max_err_over_e": None,
+        "refine": stats,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_with_oracle": parity,
+        "wall_s_timed_loop": round(t_wall, 3),
+    }
+    e = float(ora.inspect(s_gpu)[1]["e"])
+    line["max_err_over_e"] = round(float(np.max(np.abs(rec_gpu.astype(np.float64) - field))) / e, 6)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -11,7 +11,10 @@
  * Conventions for every call below:
  *  - Pointers named d_* are DEVICE pointers (HIP global memory on the
  *    current device); h_* are host pointers.  The caller owns every buffer;
- *    the library never allocates, frees or retains memory.
+ *    the library never allocates, frees or retains memory.  Alignment: the
+ *    input field 16 bytes, streams and sizes 8 bytes, the workspace 256
+ *    bytes, reconstructions and statuses 4 bytes (TOPOSZP_E_INVALID_ARG
+ *    otherwise).
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls are stream-ordered and asynchronous: results are valid once the
  *    stream has been synchronised.  Nothing is read back to the host.

@@ -1,24 +1,35 @@
 // libtoposzp: TopoSZp compression and decompression on MI355X (gfx950).
 //
-// Kernels (one wave of 64 lanes handles one 64-point block, lane = point):
-//   range_kernel     relative-bound pass: min/max of the field, finiteness.
-//   encode_kernel    one workgroup per chunk of 64 blocks: critical point
-//                    detection and ranks on the original values, exact
-//                    quantization, 1-D differences, per-block bit widths,
-//                    sign and bit-plane ballots, 2-bit labels; a decoupled
-//                    look-back scan over chunks places the variable-size
-//                    payload, which is written coalesced from LDS.
-//   finalize_kernel  header, rank payload move, status, workspace reset.
-//   decode_kernel    one workgroup per chunk: planes -> residuals -> in-wave
-//                    prefix sum -> bin centres, labels and ranks, the extrema
-//                    stencil (pointwise: a flattened extremum moves delta
-//                    float steps off its bin centre), flattened saddles queued.
-//   refine_kernel    cooperative: colour-phased RBF rounds over the queue,
-//                    grid barriers between phases, until a round commits
-//                    nothing.
+// One wave of 64 lanes handles one 64-point block (lane = point); a
+// workgroup handles a chunk of 64 blocks (4096 points).
 //
-// Method: Section IV of the paper (compression IV-A, decompression IV-B);
-// readings of the points the paper leaves open are stated where used.
+// Compression (Section IV-A):
+//   range_kernel     relative bound only: per-workgroup min/max partials.
+//   encode_kernel    per chunk: critical point detection and ranks on the
+//                    original values, exact quantization, 1-D differences,
+//                    per-block bit widths, sign and bit-plane ballots, 2-bit
+//                    labels; fixed-size parts written in place, the chunk's
+//                    bit planes staged compactly; chunk plane totals.
+//   scan_kernel      one workgroup: exclusive scan of the chunk totals.
+//   finalize_kernel  per chunk: staged planes to their final offsets, chunk
+//                    index; workgroup 0 writes the header and status.
+// Decompression (Section IV-B):
+//   decode_kernel    per chunk: planes -> residuals -> in-wave prefix sum ->
+//                    bin centres; labels and ranks; the extrema stencil (a
+//                    flattened extremum moves delta float steps off its bin
+//                    centre); flattened saddles queued per chunk.
+//   refine_kernel    per chunk: the RBF refinement of queued saddles.
+//                    Queued saddles that cannot influence each other's
+//                    evaluation evolve independently under the colour-phased
+//                    schedule, so an isolated saddle is settled by a single
+//                    evaluation and a small cluster by one thread replaying
+//                    the schedule on its members.
+//   tail_kernel      cooperative: the same schedule with grid barriers for
+//                    the rare clusters too large for one thread; status and
+//                    counters.
+//
+// No kernel contends on a single global address; every device wait is
+// bounded.  Readings of points the paper leaves open are stated where used.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,61 +50,87 @@ constexpr int kMaxWRankBlk = 7;        // block-scope ranks lie in [0, 64]
 constexpr int kMaxWRankAny = 31;       // field-scope ranks lie in [0, N]
 constexpr int kNSeg = 13;
 constexpr int kMaxRounds = 65535;
-constexpr int kSingleMax = 2048;       // refine with one workgroup up to this
+constexpr int kChunk = kB * kB;        // points per chunk
+constexpr int kRangeWG = 512;          // max range-pass workgroups
+constexpr int kClusterMax = 32;        // cluster members one thread replays
+constexpr int kRefineThreads = 128;
+constexpr int kSpreadLines = 64;       // counters spread over cache lines
+constexpr unsigned kSpinLimit = 1u << 22;
 enum { S1, S2, S3, S4, S6, R1, R2, R3, R4, X1, X2, S5, R5 };
 enum { CLS_R = 0, CLS_MIN = 1, CLS_SAD = 2, CLS_MAX = 3 };
 
 // ---------------------------------------------------------------------------
-// Workspace layout.  Control block first, then the per-round commit counters
-// (decompression), then a region shared by the compressor (look-back words,
-// staged rank planes) and the decompressor (saddle queue).
+// Workspace layout: control block, spread counters, per-round counters of
+// the cooperative tail, range partials, then a region whose layout depends
+// on the call's field size (each call writes what it reads there).
 
-struct Plan {                 // decode -> refine hand-off
-  int valid, topo, ndim, k, ncol, max_rounds, twostep, pad;
+struct Plan {                 // decode -> refine/tail hand-off
+  int valid, topo, ndim, k, ncol, max_rounds, twostep, nch;
   int n, nx, ny, nz;
   float e;
   float w[10];
   uint64_t s6_off;
-  uint64_t wl_cap;
 };
 
 struct Ctrl {
-  // compression
-  unsigned ticket;            // chunk tickets (dispatch order)
-  unsigned vmin_u, vmax_u;    // order-preserving keys of the range
-  unsigned cflags;            // 1 non-finite, 2 bound out of range, 4 |q| too big
+  // compression: written by scan_kernel, read by finalize_kernel
   unsigned long long tot_data, tot_rank;
-  unsigned done_fin;
-  unsigned timeout;            // a bounded wait gave up (reported as E_DEVICE)
-  unsigned pad0[6];
+  unsigned cflags;            // 1 non-finite, 2 bound out of range, 4 |q| too big
+  float e, vmin, vmax;
+  double eps;
   // decompression
-  unsigned dflags;            // 1 corrupt, 2 capacity
-  unsigned wl_count;
-  unsigned bar;               // grid barrier arrivals
-  unsigned done_ref;
-  unsigned rounds_used;
-  unsigned pad1[3];
-  unsigned long long st_moves, st_skips;
-  unsigned long long stats[5];// last decompression: rounds, commits, queued, moves, skips
+  unsigned hflags;            // header check of this call: 0 good, 1 corrupt, 2 capacity
+  unsigned big_count;         // saddles in clusters left to the tail kernel
+  unsigned bar;               // tail grid barrier arrivals
+  unsigned timeout;           // a bounded wait gave up
+  unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
   Plan plan;
 };
-static_assert(sizeof(Ctrl) <= 1024, "control block");
+static_assert(sizeof(Ctrl) <= 1024 - 16, "control block");
 
-constexpr size_t kCtrlBytes = 1024;
-constexpr size_t kRcOff = kCtrlBytes;                              // u32[kMaxRounds + 2]
-constexpr size_t kRegionOff = (kRcOff + 4 * (kMaxRounds + 2) + 255) & ~size_t(255);
-constexpr unsigned kSpinLimit = 1u << 22;  // bounded waits: ~seconds, then E_DEVICE
+struct Spread {               // one cache line each
+  unsigned commits, rounds, queued, pad[13];
+};
 
-// The compressor's look-back words sit in their own area right after the
-// counters, sized from the workspace size so that no field that fits the
-// workspace can need more (a workspace of W bytes serves at most W/10
-// points, i.e. W/40960 + 1 chunks); the rank-plane staging (compression) and
-// the saddle queue (decompression) share the area after it.
-__host__ __device__ constexpr uint64_t lookback_bytes(uint64_t ws_bytes) {
-  return ((ws_bytes / 40960 + 2) * 8 + 255) & ~uint64_t(255);
+constexpr size_t kSpreadOff = 1024;
+constexpr size_t kRcOff = kSpreadOff + sizeof(Spread) * kSpreadLines;
+constexpr size_t kPartOff = (kRcOff + 4 * (kMaxRounds + 2) + 255) & ~size_t(255);
+constexpr size_t kRegionOff = (kPartOff + 16 * kRangeWG + 255) & ~size_t(255);
+
+__host__ __device__ constexpr uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct CompLayout {
+  uint64_t tot_d, tot_r, cflag, stage_d, stage_r, end;
+};
+__host__ __device__ inline CompLayout comp_layout(uint64_t nch) {
+  CompLayout L;
+  L.tot_d = kRegionOff;
+  L.tot_r = L.tot_d + 4 * nch;
+  L.cflag = L.tot_r + 4 * nch;
+  L.stage_d = al256(L.cflag + 4 * nch);
+  L.stage_r = al256(L.stage_d + 8ull * kB * kMaxWData * nch);
+  L.end = al256(L.stage_r + 8ull * kB * kMaxWRankBlk * nch);
+  return L;
 }
-__host__ __device__ constexpr uint64_t shared_off(uint64_t ws_bytes) {
-  return kRegionOff + lookback_bytes(ws_bytes);
+
+struct DecLayout {
+  uint64_t cnt, moves, skips, dflag, bitmap, idx, col, state, pend, big, end;
+};
+__host__ __device__ inline DecLayout dec_layout(uint64_t nb, uint64_t nch) {
+  DecLayout L;
+  const uint64_t slots = nch * kChunk;
+  L.cnt = kRegionOff;
+  L.moves = L.cnt + 4 * nch;
+  L.skips = L.moves + 4 * nch;
+  L.dflag = L.skips + 4 * nch;
+  L.bitmap = al256(L.dflag + 4 * nch);
+  L.idx = al256(L.bitmap + 8 * nb);
+  L.col = al256(L.idx + 4 * slots);
+  L.state = al256(L.col + slots);
+  L.pend = al256(L.state + slots);
+  L.big = al256(L.pend + 4 * slots);
+  L.end = al256(L.big + 4 * slots);
+  return L;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,7 +142,7 @@ __device__ __forceinline__ int fkey(float x) {
   return b >= 0 ? b : (int)(0x80000000u - (unsigned)b);
 }
 __device__ __forceinline__ float key2f(long long k) {
-  if (k > 0x7F800000LL) k = 0x7F800001LL;     // past +inf: not a finite value
+  if (k > 0x7F800000LL) k = 0x7F800001LL;  // past +inf: not a finite value
   if (k < -0x7F800000LL) k = -0x7F800001LL;
   unsigned b = k >= 0 ? (unsigned)k : 0x80000000u + (unsigned)(-k);
   return __int_as_float((int)b);
@@ -190,9 +227,11 @@ __device__ __forceinline__ int encode_block(int v, int lane, unsigned long long*
   sign = __ballot(r < 0);
   const unsigned mag = (unsigned)(r < 0 ? -r : r);
   const unsigned mx = wave_max_u(mag);
-  const int w0 = mx ? 32 - __clz((int)mx) : 0;
-  int w = w0;
-  if (w > MAXW) { over = true; w = MAXW; }
+  int w = mx ? 32 - __clz((int)mx) : 0;
+  if (w > MAXW) {
+    over = true;
+    w = MAXW;
+  }
   unsigned long long mine = 0;
   for (int j = 0; j < w; ++j) {
     const unsigned long long pl = __ballot((mag >> j) & 1u);
@@ -217,13 +256,6 @@ __device__ __forceinline__ int decode_block(const uint8_t* planes, int w, int fi
   return wave_incl_scan(r, lane);
 }
 
-__device__ __forceinline__ unsigned long long ld_acq(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // ---------------------------------------------------------------------------
 // Kernel arguments.
 
@@ -235,25 +267,29 @@ struct EncArgs {
   const float* f;
   uint8_t* out;
   uint8_t* ws;
-  uint64_t ws_bytes;
   Geom g;
-  int nb, nch, topo, eb_mode, rbf_policy, max_rounds;
+  int nb, nch, topo, eb_mode, nrange;
   double eb;
   float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
 };
 
+struct ScanArgs {
+  uint8_t* ws;
+  int nch, eb_mode, nrange;
+  double eb;
+  float e_abs;
+};
+
 struct FinArgs {
   uint8_t* out;
   uint8_t* ws;
-  uint64_t ws_bytes;
   uint64_t* out_size;
   int32_t* status;
   Geom g;
   uint64_t dims[3];
   int nb, nch, topo, eb_mode, rbf_policy, max_rounds;
   double eb;
-  float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
   float wtab[3][10];
 };
@@ -271,11 +307,13 @@ struct RefArgs {
   const uint8_t* in;
   float* out;
   uint8_t* ws;
-  uint64_t ws_bytes;
   int32_t* status;
 };
 
 __device__ __forceinline__ Ctrl* ctrl_of(uint8_t* ws) { return reinterpret_cast<Ctrl*>(ws); }
+__device__ __forceinline__ Spread* spread_of(uint8_t* ws) {
+  return reinterpret_cast<Spread*>(ws + kSpreadOff);
+}
 
 // Segment lengths and offsets: fixed-size parts first (offsets depend on the
 // block count only), the two variable-size payloads last.
@@ -312,15 +350,9 @@ __global__ void ws_init_kernel(uint8_t* ws, uint64_t nbytes) {
     p[i] = 0;
 }
 
-// range accumulators start at the neutral keys
-__global__ void ws_init_keys_kernel(uint8_t* ws) {
-  Ctrl* c = ctrl_of(ws);
-  c->vmin_u = 0xFFFFFFFFu;
-  c->vmax_u = 0u;
-}
-
 // ---------------------------------------------------------------------------
-// Relative-bound range pass.
+// Relative-bound range pass: one partial (min key, max key, non-finite) per
+// workgroup; consumers reduce the partials.
 
 __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f, int n, uint8_t* ws) {
   __shared__ unsigned s_lo[4], s_hi[4], s_bad[4];
@@ -330,16 +362,13 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
   const int stride = gridDim.x * blockDim.x;
   const int n4 = n / 4;
   const float4* f4 = reinterpret_cast<const float4*>(f);
-  const bool aligned = (reinterpret_cast<uintptr_t>(f) & 15) == 0;
-  if (aligned) {
-    for (int i = blockIdx.x * blockDim.x + tid; i < n4; i += stride) {
-      const float4 v = f4[i];
-      bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
-      lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-      hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
-    }
+  for (int i = blockIdx.x * blockDim.x + tid; i < n4; i += stride) {
+    const float4 v = f4[i];
+    bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+    lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+    hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
   }
-  for (int i = (aligned ? 4 * n4 : 0) + blockIdx.x * blockDim.x + tid; i < n; i += stride) {
+  for (int i = 4 * n4 + blockIdx.x * blockDim.x + tid; i < n; i += stride) {
     const float v = f[i];
     bad |= !isfinite(v);
     lo = fminf(lo, v);
@@ -365,24 +394,44 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
       b = max(b, s_hi[k]);
       c |= s_bad[k];
     }
-    Ctrl* ct = ctrl_of(ws);
-    atomicMin(&ct->vmin_u, a);
-    atomicMax(&ct->vmax_u, b);
-    if (c) atomicOr(&ct->cflags, 1u);
+    unsigned* p = reinterpret_cast<unsigned*>(ws + kPartOff + 16 * (size_t)blockIdx.x);
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
   }
 }
 
-// Absolute bound e (float) of the call, from the range pass or the host.
-__device__ __forceinline__ double bound_eps(const Ctrl* ct, int eb_mode, double eb, float& vmin,
-                                            float& vmax) {
-  vmin = 0.0f;
-  vmax = 0.0f;
+// Bound of the call (one wave): relative mode reduces the range partials.
+__device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_abs, int nrange,
+                           int lane, float* e, float* vmin, float* vmax, double* eps, bool* bad) {
+  unsigned lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
   if (eb_mode == TOPOSZP_EB_REL) {
-    vmin = ukey2f(ct->vmin_u);
-    vmax = ukey2f(ct->vmax_u);
-    if (vmax > vmin) return eb * ((double)vmax - (double)vmin);
+    for (int k = lane; k < nrange; k += 64) {
+      const unsigned* p = reinterpret_cast<const unsigned*>(ws + kPartOff + 16 * (size_t)k);
+      lo = min(lo, p[0]);
+      hi = max(hi, p[1]);
+      nf |= p[2];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = min(lo, (unsigned)__shfl_xor((int)lo, o));
+      hi = max(hi, (unsigned)__shfl_xor((int)hi, o));
+      nf |= (unsigned)__shfl_xor((int)nf, o);
+    }
   }
-  return eb;
+  if (eb_mode == TOPOSZP_EB_REL) {
+    const float a = ukey2f(lo), b = ukey2f(hi);
+    *vmin = a;
+    *vmax = b;
+    *eps = (b > a) ? eb * ((double)b - (double)a) : eb;
+    *e = round_down_f(*eps);
+  } else {
+    *vmin = 0.0f;
+    *vmax = 0.0f;
+    *eps = eb;
+    *e = e_abs;
+  }
+  *bad = nf != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -395,27 +444,22 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   __shared__ unsigned long long s_pr[kB][kMaxWRankBlk];
   __shared__ int s_wd[kB], s_wr[kB];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1];
-  __shared__ unsigned s_chunk;
   __shared__ float s_e;
-  __shared__ unsigned long long s_exd, s_exr;
   __shared__ unsigned s_flags;
 
-  Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) {
-    s_chunk = atomicAdd(&ct->ticket, 1u);
-    float e;
-    if (a.eb_mode == TOPOSZP_EB_REL) {
-      float vmin, vmax;
-      e = round_down_f(bound_eps(ct, a.eb_mode, a.eb, vmin, vmax));
-    } else {
-      e = a.e_abs;
+  const int c = blockIdx.x;
+  if (wv == 0) {
+    float e, vmin, vmax;
+    double eps;
+    bool nf;
+    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
+    if (lane == 0) {
+      s_e = e;
+      s_flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
     }
-    s_e = e;
-    s_flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
   }
   __syncthreads();
-  const int c = (int)s_chunk;
   const float e = s_e;
   const double ed = (double)e;
   const float inv2e = 1.0f / (2.0f * e);
@@ -541,7 +585,8 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   }
   __syncthreads();
 
-  // chunk: constant-block bitmaps, local prefix of widths, look-back
+  // chunk: constant-block bitmaps, local prefix of widths, chunk totals
+  const CompLayout L = comp_layout((uint64_t)a.nch);
   if (wv == 0) {
     const int b = c * kB + lane;
     const bool bv = b < a.nb;
@@ -556,53 +601,18 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
       *reinterpret_cast<unsigned long long*>(a.out + a.off[S1] + 8 * (size_t)c) = cb;
       if (a.topo) *reinterpret_cast<unsigned long long*>(a.out + a.off[R1] + 8 * (size_t)c) = cr;
     }
-    const unsigned long long totd = (unsigned)__builtin_amdgcn_readlane(sd, 63);
-    const unsigned long long totr = (unsigned)__builtin_amdgcn_readlane(sr, 63);
-    if (lane == 0) {
-      unsigned long long* lbw = reinterpret_cast<unsigned long long*>(a.ws + kRegionOff);
-      const unsigned long long agg = (totd << 31) | totr;
-      unsigned long long exd = 0, exr = 0;
-      if (c == 0) {
-        st_rel(&lbw[0], (2ull << 62) | agg);
-      } else {
-        st_rel(&lbw[c], (1ull << 62) | agg);
-        int j = c - 1;
-        unsigned spins = 0;
-        while (j >= 0) {
-          const unsigned long long wv2 = ld_acq(&lbw[j]);
-          const unsigned st = (unsigned)(wv2 >> 62);
-          if (st == 0) {
-            if (++spins > kSpinLimit) {
-              atomicOr(&ct->timeout, 1u);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          exd += (wv2 >> 31) & 0x7FFFFFFFull;
-          exr += wv2 & 0x7FFFFFFFull;
-          if (st == 2) break;
-          --j;
-        }
-        st_rel(&lbw[c], (2ull << 62) | ((exd + totd) << 31) | (exr + totr));
-      }
-      s_exd = exd;
-      s_exr = exr;
-      *reinterpret_cast<unsigned long long*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * exd;
-      if (a.topo) *reinterpret_cast<unsigned long long*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * exr;
-      if (c == a.nch - 1) {
-        ct->tot_data = exd + totd;
-        ct->tot_rank = exr + totr;
-      }
-      if (s_flags) atomicOr(&ct->cflags, s_flags);
+    if (lane == 63) {
+      reinterpret_cast<unsigned*>(a.ws + L.tot_d)[c] = (unsigned)sd;
+      reinterpret_cast<unsigned*>(a.ws + L.tot_r)[c] = (unsigned)sr;
+      reinterpret_cast<unsigned*>(a.ws + L.cflag)[c] = s_flags;
     }
   }
   __syncthreads();
 
-  // payload: this chunk's planes, contiguous, coalesced from LDS
+  // this chunk's planes, compact, to its staging slot (coalesced from LDS)
   {
     const int totd = s_pfd[kB];
-    uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + s_exd;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(a.ws + L.stage_d) + (size_t)c * kB * kMaxWData;
     for (int o = tid; o < totd; o += WAVES * 64) {
       int lo = 0, hi = kB;  // find lb with s_pfd[lb] <= o < s_pfd[lb+1]
       while (hi - lo > 1) {
@@ -613,7 +623,7 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
     }
     if (a.topo) {
       const int totr = s_pfr[kB];
-      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.ws + shared_off(a.ws_bytes)) + s_exr;
+      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * kMaxWRankBlk;
       for (int o = tid; o < totr; o += WAVES * 64) {
         int lo = 0, hi = kB;
         while (hi - lo > 1) {
@@ -632,8 +642,84 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   }
 }
 
+// Exclusive scan of the chunk plane totals (in place), flags, and the bound.
+__global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
+  __shared__ unsigned long long s_w[2][16];
+  __shared__ unsigned long long s_carry[2];
+  __shared__ unsigned s_fl;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const CompLayout L = comp_layout((uint64_t)a.nch);
+  unsigned* td = reinterpret_cast<unsigned*>(a.ws + L.tot_d);
+  unsigned* tr = reinterpret_cast<unsigned*>(a.ws + L.tot_r);
+  const unsigned* cf = reinterpret_cast<const unsigned*>(a.ws + L.cflag);
+  Ctrl* ct = ctrl_of(a.ws);
+  if (tid == 0) {
+    s_carry[0] = 0;
+    s_carry[1] = 0;
+    s_fl = 0;
+  }
+  __syncthreads();
+  unsigned fl = 0;
+  for (int base = 0; base < a.nch; base += 1024) {
+    const int c = base + tid;
+    const bool v = c < a.nch;
+    const unsigned long long xd = v ? td[c] : 0, xr = v ? tr[c] : 0;
+    if (v) fl |= cf[c];
+    unsigned long long sd = xd, sr = xr;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t1 = __shfl_up(sd, o), t2 = __shfl_up(sr, o);
+      if (lane >= o) {
+        sd += t1;
+        sr += t2;
+      }
+    }
+    if (lane == 63) {
+      s_w[0][wv] = sd;
+      s_w[1][wv] = sr;
+    }
+    __syncthreads();
+    unsigned long long od = s_carry[0], orr = s_carry[1];
+    for (int k = 0; k < wv; ++k) {
+      od += s_w[0][k];
+      orr += s_w[1][k];
+    }
+    if (v) {
+      td[c] = (unsigned)(od + sd - xd);
+      tr[c] = (unsigned)(orr + sr - xr);
+    }
+    __syncthreads();
+    if (tid == 1023) {
+      s_carry[0] = od + sd;
+      s_carry[1] = orr + sr;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) fl |= (unsigned)__shfl_xor((int)fl, o);
+  if (lane == 0 && fl) atomicOr(&s_fl, fl);
+  __syncthreads();
+  if (wv == 0) {
+    float e, vmin, vmax;
+    double eps;
+    bool nf;
+    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
+    if (lane == 0) {
+      unsigned flags = s_fl | (nf ? 1u : 0u);
+      if (!(e >= 0x1p-100f && e <= 0x1p100f)) flags |= 2u;
+      ct->tot_data = s_carry[0];
+      ct->tot_rank = s_carry[1];
+      ct->cflags = flags;
+      ct->e = e;
+      ct->vmin = vmin;
+      ct->vmax = vmax;
+      ct->eps = eps;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Finalize: header, rank payload, status, reset.
+// Finalize: payload placement, chunk index, header, status.
 
 __device__ void put8(uint8_t* h, int off, uint64_t v) { memcpy(h + off, &v, 8); }
 __device__ void put4(uint8_t* h, int off, uint32_t v) { memcpy(h + off, &v, 4); }
@@ -642,117 +728,104 @@ __device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   __shared__ uint8_t hdr[kHdr];
   __shared__ unsigned s_sa[4], s_sb[4];
-  Ctrl* ct = ctrl_of(a.ws);
+  const Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
-  const uint64_t td = ct->tot_data, tr = a.topo ? ct->tot_rank : 0;
-  const uint64_t off_r5 = a.off[S5] + 8 * td;
-  const uint64_t* stage = reinterpret_cast<const uint64_t*>(a.ws + shared_off(a.ws_bytes));
-  uint64_t* r5 = reinterpret_cast<uint64_t*>(a.out + off_r5);
-  const uint64_t gt = blockIdx.x * (uint64_t)blockDim.x + tid, gs = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t o = gt; o < tr; o += gs) r5[o] = stage[o];
-  // look-back words back to zero for the next call
-  unsigned long long* lbw = reinterpret_cast<unsigned long long*>(a.ws + kRegionOff);
-  for (uint64_t o = gt; o < (uint64_t)a.nch; o += gs) lbw[o] = 0;
-
-  if (blockIdx.x == 0) {
-    const unsigned flags = ct->cflags;
-    float vmin, vmax;
-    const double eps = bound_eps(ct, a.eb_mode, a.eb, vmin, vmax);
-    const float e = a.eb_mode == TOPOSZP_EB_REL ? round_down_f(eps) : a.e_abs;
-    int status = TOPOSZP_OK;
-    if (ct->timeout) status = TOPOSZP_E_DEVICE;
-    else if (flags & 1u) status = TOPOSZP_E_NONFINITE;
-    else if (flags & 6u) status = TOPOSZP_E_RANGE;
-    for (int k = tid; k < kHdr; k += blockDim.x) hdr[k] = 0;
-    __syncthreads();
-    uint64_t total = 0;
-    if (tid == 0) {
-      int k = 3;
-      float sigma = 0.5f;
-      int si = 0;
-      if (a.rbf_policy == 0 && td <= (uint64_t)a.nb) { k = 7; sigma = 1.0f; si = 2; }
-      else if (a.rbf_policy == 0 && td <= 3 * (uint64_t)a.nb) { k = 5; sigma = 0.75f; si = 1; }
-      uint64_t off[kNSeg], len[kNSeg];
-      total = seg_layout((uint64_t)a.nb, a.topo, td, tr, off, len);
-      hdr[0] = 'T'; hdr[1] = 'S'; hdr[2] = 'Z'; hdr[3] = '1';
-      put2(hdr, 4, 1);
-      hdr[6] = (uint8_t)a.g.ndim;
-      hdr[7] = (uint8_t)(a.topo ? 1 : 0);
-      for (int d = 0; d < 3; ++d) put8(hdr, 8 + 8 * d, a.dims[d]);
-      put8(hdr, 32, (uint64_t)a.g.n);
-      put8(hdr, 40, (uint64_t)a.nb);
-      put4(hdr, 48, kB);
-      hdr[52] = (uint8_t)a.eb_mode;
-      hdr[53] = (uint8_t)k;
-      put2(hdr, 54, (uint16_t)a.max_rounds);
-      uint64_t u;
-      memcpy(&u, &a.eb, 8); put8(hdr, 56, u);
-      memcpy(&u, &eps, 8); put8(hdr, 64, u);
-      uint32_t v;
-      memcpy(&v, &e, 4); put4(hdr, 72, v);
-      memcpy(&v, &vmin, 4); put4(hdr, 76, v);
-      memcpy(&v, &vmax, 4); put4(hdr, 80, v);
-      memcpy(&v, &sigma, 4); put4(hdr, 84, v);
-      for (int d2 = 0; d2 < 10; ++d2) { memcpy(&v, &a.wtab[si][d2], 4); put4(hdr, 88 + 4 * d2, v); }
-      put8(hdr, 128, total);
-      put8(hdr, 136, td);
-      put8(hdr, 144, tr);
-      put8(hdr, 152, (uint64_t)a.nch);
-      for (int s = 0; s < kNSeg; ++s) {
-        put8(hdr, 160 + 8 * s, off[s]);
-        put8(hdr, 264 + 8 * s, len[s]);
-      }
-      *a.status = status;
-      *a.out_size = status == TOPOSZP_OK ? total : 0;
+  const int c = blockIdx.x;
+  const CompLayout L = comp_layout((uint64_t)a.nch);
+  const uint64_t totd = ct->tot_data, totr = a.topo ? ct->tot_rank : 0;
+  const unsigned* pd = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
+  const unsigned* pr = reinterpret_cast<const unsigned*>(a.ws + L.tot_r);
+  {
+    const uint64_t b0 = pd[c], b1 = c + 1 < a.nch ? pd[c + 1] : totd;
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(a.ws + L.stage_d) + (size_t)c * kB * kMaxWData;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + b0;
+    for (uint64_t o = tid; o < b1 - b0; o += blockDim.x) dst[o] = src[o];
+    if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * b0;
+    if (a.topo) {
+      const uint64_t r0 = pr[c], r1 = c + 1 < a.nch ? pr[c + 1] : totr;
+      const uint64_t* rsrc =
+          reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * kMaxWRankBlk;
+      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.out + a.off[S5] + 8 * totd) + r0;
+      for (uint64_t o = tid; o < r1 - r0; o += blockDim.x) rdst[o] = rsrc[o];
+      if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * r0;
     }
-    __syncthreads();
-    // Adler-32 of bytes [0, 376): A = 1 + sum b_i, B = n + sum (n - i) b_i (mod 65521)
-    unsigned sa = 0, sb = 0;
-    for (int i = tid; i < kSummed; i += blockDim.x) {
-      sa += hdr[i];
-      sb += (unsigned)(kSummed - i) * hdr[i];
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      sa += (unsigned)__shfl_xor((int)sa, o);
-      sb += (unsigned)__shfl_xor((int)sb, o);
-    }
-    if ((tid & 63) == 0) {
-      s_sa[tid >> 6] = sa;
-      s_sb[tid >> 6] = sb;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint64_t A = 1, B = kSummed;
-      for (int k = 0; k < (int)(blockDim.x / 64); ++k) {
-        A += s_sa[k];
-        B += s_sb[k];
-      }
-      A %= 65521u;
-      B %= 65521u;
-      put4(hdr, kSummed, (uint32_t)((B << 16) | A));
-    }
-    __syncthreads();
-    for (int k = tid; k < kHdr; k += blockDim.x) a.out[k] = hdr[k];
   }
+  if (c != 0) return;
 
-  // the last workgroup to finish resets the control block
+  const unsigned flags = ct->cflags;
+  int status = TOPOSZP_OK;
+  if (flags & 1u) status = TOPOSZP_E_NONFINITE;
+  else if (flags & 6u) status = TOPOSZP_E_RANGE;
+  for (int k = tid; k < kHdr; k += blockDim.x) hdr[k] = 0;
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
-    const unsigned d = __hip_atomic_fetch_add(&ct->done_fin, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (d == gridDim.x - 1) {
-      ct->ticket = 0;
-      ct->vmin_u = 0xFFFFFFFFu;
-      ct->vmax_u = 0u;
-      ct->cflags = 0;
-      ct->timeout = 0;
-      ct->tot_data = 0;
-      ct->tot_rank = 0;
-      __threadfence();
-      ct->done_fin = 0;
+    int k = 3;
+    float sigma = 0.5f;
+    int si = 0;
+    if (a.rbf_policy == 0 && totd <= (uint64_t)a.nb) { k = 7; sigma = 1.0f; si = 2; }
+    else if (a.rbf_policy == 0 && totd <= 3 * (uint64_t)a.nb) { k = 5; sigma = 0.75f; si = 1; }
+    uint64_t off[kNSeg], len[kNSeg];
+    const uint64_t total = seg_layout((uint64_t)a.nb, a.topo, totd, totr, off, len);
+    hdr[0] = 'T'; hdr[1] = 'S'; hdr[2] = 'Z'; hdr[3] = '1';
+    put2(hdr, 4, 1);
+    hdr[6] = (uint8_t)a.g.ndim;
+    hdr[7] = (uint8_t)(a.topo ? 1 : 0);
+    for (int d = 0; d < 3; ++d) put8(hdr, 8 + 8 * d, a.dims[d]);
+    put8(hdr, 32, (uint64_t)a.g.n);
+    put8(hdr, 40, (uint64_t)a.nb);
+    put4(hdr, 48, kB);
+    hdr[52] = (uint8_t)a.eb_mode;
+    hdr[53] = (uint8_t)k;
+    put2(hdr, 54, (uint16_t)a.max_rounds);
+    uint64_t u;
+    memcpy(&u, &a.eb, 8); put8(hdr, 56, u);
+    memcpy(&u, &ct->eps, 8); put8(hdr, 64, u);
+    uint32_t v;
+    memcpy(&v, &ct->e, 4); put4(hdr, 72, v);
+    memcpy(&v, &ct->vmin, 4); put4(hdr, 76, v);
+    memcpy(&v, &ct->vmax, 4); put4(hdr, 80, v);
+    memcpy(&v, &sigma, 4); put4(hdr, 84, v);
+    for (int d2 = 0; d2 < 10; ++d2) { memcpy(&v, &a.wtab[si][d2], 4); put4(hdr, 88 + 4 * d2, v); }
+    put8(hdr, 128, total);
+    put8(hdr, 136, totd);
+    put8(hdr, 144, totr);
+    put8(hdr, 152, (uint64_t)a.nch);
+    for (int s = 0; s < kNSeg; ++s) {
+      put8(hdr, 160 + 8 * s, off[s]);
+      put8(hdr, 264 + 8 * s, len[s]);
     }
+    *a.status = status;
+    *a.out_size = status == TOPOSZP_OK ? total : 0;
   }
+  __syncthreads();
+  // Adler-32 of bytes [0, 376): A = 1 + sum b_i, B = n + sum (n - i) b_i (mod 65521)
+  unsigned sa = 0, sb = 0;
+  for (int i = tid; i < kSummed; i += blockDim.x) {
+    sa += hdr[i];
+    sb += (unsigned)(kSummed - i) * hdr[i];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    sa += (unsigned)__shfl_xor((int)sa, o);
+    sb += (unsigned)__shfl_xor((int)sb, o);
+  }
+  if ((tid & 63) == 0) {
+    s_sa[tid >> 6] = sa;
+    s_sb[tid >> 6] = sb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t A = 1, B = kSummed;
+    for (int k = 0; k < (int)(blockDim.x / 64); ++k) {
+      A += s_sa[k];
+      B += s_sb[k];
+    }
+    A %= 65521u;
+    B %= 65521u;
+    put4(hdr, kSummed, (uint32_t)((B << 16) | A));
+  }
+  __syncthreads();
+  for (int k = tid; k < kHdr; k += blockDim.x) a.out[k] = hdr[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -772,18 +845,24 @@ __device__ __forceinline__ T rd(const uint8_t* p, int off) {
   return v;
 }
 
-// Header checks (one wave): checksum, field ranges and the segment table
-// against the layout rule.  Result in *h (LDS); h->ok = 0 corrupt,
-// -1 capacity, 1 good.
+// Header checks (one wave): the header is copied to LDS in parallel, then
+// lane 0 checks the checksum, field ranges and the segment table against the
+// layout rule.  Result in *h: ok = 0 corrupt, -1 capacity, 1 good.
 __device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_cap, Hdr* h,
-                             int lane) {
-  bool good = in_size >= (uint64_t)kHdr;
+                             uint8_t* hb, int lane) {
+  const bool good = in_size >= (uint64_t)kHdr;
   unsigned sa = 0, sb = 0;
   if (good) {
-    for (int i = lane; i < kSummed; i += 64) {
-      const unsigned b = in[i];
-      sa += b;
-      sb += (unsigned)(kSummed - i) * b;
+    // 512 header bytes: 8 per lane
+    const uint64_t w = *reinterpret_cast<const uint64_t*>(in + 8 * lane);
+    *reinterpret_cast<uint64_t*>(hb + 8 * lane) = w;
+    for (int j = 0; j < 8; ++j) {
+      const int i = 8 * lane + j;
+      const unsigned b = (unsigned)((w >> (8 * j)) & 0xFFu);
+      if (i < kSummed) {
+        sa += b;
+        sb += (unsigned)(kSummed - i) * b;
+      }
     }
   }
 #pragma unroll
@@ -791,50 +870,53 @@ __device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_c
     sa += (unsigned)__shfl_xor((int)sa, o);
     sb += (unsigned)__shfl_xor((int)sb, o);
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane != 0) return;
   h->ok = 0;
   if (!good) return;
   const uint32_t adler = (uint32_t)((((uint64_t)kSummed + sb) % 65521u) << 16 | ((1ull + sa) % 65521u));
-  if (in[0] != 'T' || in[1] != 'S' || in[2] != 'Z' || in[3] != '1') return;
-  if (rd<uint16_t>(in, 4) != 1) return;
-  if (rd<uint32_t>(in, kSummed) != adler || rd<uint32_t>(in, kSummed + 4) != 0) return;
-  h->ndim = in[6];
+  if (hb[0] != 'T' || hb[1] != 'S' || hb[2] != 'Z' || hb[3] != '1') return;
+  if (rd<uint16_t>(hb, 4) != 1) return;
+  if (rd<uint32_t>(hb, kSummed) != adler || rd<uint32_t>(hb, kSummed + 4) != 0) return;
+  h->ndim = hb[6];
   if (h->ndim != 2 && h->ndim != 3) return;
-  if (in[7] & ~3u) return;
-  h->topo = in[7] & 1;
-  h->scope = (in[7] >> 1) & 1;
+  if (hb[7] & ~3u) return;
+  h->topo = hb[7] & 1;
+  h->scope = (hb[7] >> 1) & 1;
   uint64_t prod = 1;
   for (int d = 0; d < 3; ++d) {
-    h->dims[d] = rd<uint64_t>(in, 8 + 8 * d);
+    h->dims[d] = rd<uint64_t>(hb, 8 + 8 * d);
     if (h->dims[d] < 1 || h->dims[d] > (1ull << 31)) return;
     if (d >= h->ndim && h->dims[d] != 1) return;
     prod *= h->dims[d];
     if (prod >= (1ull << 31)) return;
   }
-  h->n = rd<uint64_t>(in, 32);
-  h->nb = rd<uint64_t>(in, 40);
-  h->nch = rd<uint64_t>(in, 152);
+  h->n = rd<uint64_t>(hb, 32);
+  h->nb = rd<uint64_t>(hb, 40);
+  h->nch = rd<uint64_t>(hb, 152);
   if (h->n != prod || h->nb != (h->n + kB - 1) / kB || h->nch != (h->nb + kB - 1) / kB) return;
-  if (rd<uint32_t>(in, 48) != (uint32_t)kB) return;
-  h->k = in[53];
-  h->max_rounds = rd<uint16_t>(in, 54);
-  if (in[52] > 1 || (h->k != 3 && h->k != 5 && h->k != 7) || h->max_rounds < 1) return;
-  h->e = rd<float>(in, 72);
+  if (rd<uint32_t>(hb, 48) != (uint32_t)kB) return;
+  h->k = hb[53];
+  h->max_rounds = rd<uint16_t>(hb, 54);
+  if (hb[52] > 1 || (h->k != 3 && h->k != 5 && h->k != 7) || h->max_rounds < 1) return;
+  h->e = rd<float>(hb, 72);
   if (!(h->e >= 0x1p-100f) || !(h->e <= 0x1p100f)) return;
   for (int d2 = 0; d2 < 10; ++d2) {
-    h->w[d2] = rd<float>(in, 88 + 4 * d2);
+    h->w[d2] = rd<float>(hb, 88 + 4 * d2);
     if (!(h->w[d2] > 0.0f) || !(h->w[d2] <= 1.0f)) return;
   }
-  h->total = rd<uint64_t>(in, 128);
-  h->wdata = rd<uint64_t>(in, 136);
-  h->wrank = rd<uint64_t>(in, 144);
+  h->total = rd<uint64_t>(hb, 128);
+  h->wdata = rd<uint64_t>(hb, 136);
+  h->wrank = rd<uint64_t>(hb, 144);
   if (h->wdata > h->nb * kMaxWData || h->wrank > h->nb * kMaxWRankAny) return;
   uint64_t off[kNSeg], len[kNSeg];
   const uint64_t total = seg_layout(h->nb, h->topo, h->wdata, h->wrank, off, len);
   if (total != h->total || total > in_size) return;
   for (int s = 0; s < kNSeg; ++s) {
-    h->off[s] = rd<uint64_t>(in, 160 + 8 * s);
-    h->len[s] = rd<uint64_t>(in, 264 + 8 * s);
+    h->off[s] = rd<uint64_t>(hb, 160 + 8 * s);
+    h->len[s] = rd<uint64_t>(hb, 264 + 8 * s);
     if (h->off[s] != off[s] || h->len[s] != len[s]) return;
   }
   h->ok = (h->n <= out_cap) ? 1 : -1;
@@ -844,51 +926,66 @@ template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
   constexpr int BPW = kB / WAVES;
   __shared__ Hdr s_h;
+  __shared__ uint64_t s_hb[kHdr / 8];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1], s_wd[kB], s_wr[kB];
   __shared__ unsigned long long s_xd, s_xr;
   __shared__ int s_bad;
+  __shared__ unsigned s_qn, s_moves, s_skips, s_corrupt;
+  __shared__ unsigned s_qi[kChunk];
+  __shared__ uint8_t s_qc[kChunk];
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c = blockIdx.x;
-  if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, lane);
-  if (tid == 0) s_bad = 0;
+  if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, reinterpret_cast<uint8_t*>(s_hb), lane);
+  if (tid == 0) {
+    s_bad = 0;
+    s_qn = 0;
+    s_moves = 0;
+    s_skips = 0;
+    s_corrupt = 0;
+  }
   __syncthreads();
   const Hdr& h = s_h;
-  if (h.ok != 1) {
-    if (c == 0 && tid == 0) atomicOr(&ct->dflags, h.ok == -1 ? 2u : 1u);
-    return;
+  const uint64_t nb = h.ok == 1 ? h.nb : 0, nch = h.ok == 1 ? h.nch : 0;
+  const DecLayout L = dec_layout(nb, nch);
+  const bool room = h.ok == 1 && L.end <= a.ws_bytes;
+  if (c == 0 && tid == 0) {
+    // this call's header verdict and counters for refine/tail
+    ct->hflags = h.ok == 1 ? (room ? 0u : 2u) : (h.ok == -1 ? 2u : 1u);
+    ct->big_count = 0;
+    ct->bar = 0;
+    ct->timeout = 0;
+    Plan& p = ct->plan;
+    p.valid = room ? 1 : 0;
+    if (room) {
+      p.topo = h.topo;
+      p.ndim = h.ndim;
+      p.k = h.k;
+      p.ncol = h.ndim == 3 ? 7 : 5;
+      p.max_rounds = h.max_rounds;
+      // one commit step per phase when no same-colour point can read
+      // another's update (window radius 1 in 3D, up to 2 in 2D)
+      p.twostep = (h.ndim == 3) ? (h.k > 3) : (h.k > 5);
+      p.nch = (int)h.nch;
+      p.n = (int)h.n;
+      p.nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
+      p.ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
+      p.nz = h.ndim == 3 ? (int)h.dims[0] : 1;
+      p.e = h.e;
+      for (int d2 = 0; d2 < 10; ++d2) p.w[d2] = h.w[d2];
+      p.s6_off = h.off[S6];
+    }
   }
+  if (c == 0 && tid < kSpreadLines) {
+    Spread* sp = spread_of(a.ws);
+    sp[tid].commits = 0;
+    sp[tid].rounds = 0;
+    sp[tid].queued = 0;
+  }
+  if (!room || (uint64_t)c >= h.nch) return;
   const int n = (int)h.n;
   const int nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
   const int ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
-  const int nz = h.ndim == 3 ? (int)h.dims[0] : 1;
-  const int ncol = h.ndim == 3 ? 7 : 5;
-  // the saddle queue lives in the workspace: idx u32[n], colour u8[n],
-  // pending f32[n], state u8[n]
-  const uint64_t qoff = shared_off(a.ws_bytes);
-  const uint64_t need = qoff + 10ull * (uint64_t)n + 64;
-  if (c == 0 && tid == 0) {
-    Plan& p = ct->plan;
-    p.valid = need <= a.ws_bytes;
-    p.topo = h.topo;
-    p.ndim = h.ndim;
-    p.k = h.k;
-    p.ncol = ncol;
-    p.max_rounds = h.max_rounds;
-    // one barrier per phase when no same-colour point can read another's
-    // update (window radius 1 in 3D, up to 2 in 2D); two otherwise
-    p.twostep = (h.ndim == 3) ? (h.k > 3) : (h.k > 5);
-    p.n = n;
-    p.nx = nx;
-    p.ny = ny;
-    p.nz = nz;
-    p.e = h.e;
-    for (int d2 = 0; d2 < 10; ++d2) p.w[d2] = h.w[d2];
-    p.s6_off = h.off[S6];
-    p.wl_cap = (uint64_t)n;
-    if (need > a.ws_bytes) atomicOr(&ct->dflags, 2u);
-  }
-  if ((uint64_t)c >= h.nch || need > a.ws_bytes) return;
 
   // this chunk's widths, constant flags and payload offsets
   if (wv == 0) {
@@ -901,6 +998,7 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
     if (h.topo) {
       const unsigned long long cr = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R1] + 8 * (uint64_t)c);
       bad |= bv && (wr > kMaxWRankAny || (int)((cr >> lane) & 1) != (wr == 0));
+      bad |= !bv && (((cr >> lane) & 1) != 0);
     }
     bad |= !bv && (((cb >> lane) & 1) != 0);
     const int sd = wave_incl_scan(wd, lane), sr = wave_incl_scan(wr, lane);
@@ -933,15 +1031,21 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
     }
   }
   __syncthreads();
+  unsigned* dflag = reinterpret_cast<unsigned*>(a.ws + L.dflag);
+  unsigned long long* bitmap = reinterpret_cast<unsigned long long*>(a.ws + L.bitmap);
   if (s_bad) {
-    if (tid == 0) atomicOr(&ct->dflags, 1u);
+    if (tid == 0) {
+      dflag[c] = 1;
+      reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = 0;
+      reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = 0;
+      reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = 0;
+    }
+    if (tid < kB && (uint64_t)c * kB + tid < h.nb) bitmap[(uint64_t)c * kB + tid] = 0;
     return;
   }
   const double ed = (double)h.e;
   const float two_e = 2.0f * h.e;
   const int dmax = h.scope ? n : kB;
-  unsigned* wl_idx = reinterpret_cast<unsigned*>(a.ws + qoff);
-  uint8_t* wl_col = a.ws + qoff + 4ull * n;
   bool corrupt = false;
   unsigned moves = 0, skips = 0;
   for (int k = 0; k < BPW; ++k) {
@@ -979,51 +1083,73 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
       queue = valid && dl > 0 && lab == CLS_SAD;
     }
     if (valid) a.out[i] = v;
-    const unsigned long long qm = __ballot(queue);
-    if (qm) {
-      const int lead = __ffsll((long long)qm) - 1;
-      unsigned base = 0;
-      if (lane == lead) base = atomicAdd(&ct->wl_count, (unsigned)__popcll(qm));
-      base = (unsigned)__builtin_amdgcn_readlane((int)base, lead);
-      if (queue) {
-        const unsigned pos = base + mbcnt(qm);
-        const long long x = i % nx, t = i / nx, y = t % ny, z = t / ny;
-        const int col = h.ndim == 3 ? (int)((x + 2 * y + 3 * z) % 7) : (int)((x + 2 * y) % 5);
-        if (pos < (unsigned)n) {
-          wl_idx[pos] = (unsigned)i;
-          wl_col[pos] = (uint8_t)col;
+    if (h.topo) {
+      const unsigned long long qm = __ballot(queue);
+      if (lane == 0) bitmap[b] = qm;
+      if (qm) {
+        unsigned base = 0;
+        if (lane == 0) base = atomicAdd(&s_qn, (unsigned)__popcll(qm));
+        base = (unsigned)__builtin_amdgcn_readlane((int)base, 0);
+        if (queue) {
+          const unsigned pos = base + mbcnt(qm);
+          const long long x = i % nx, t = i / nx, y = t % ny, z = t / ny;
+          s_qi[pos] = (unsigned)i;
+          s_qc[pos] = (uint8_t)(h.ndim == 3 ? (x + 2 * y + 3 * z) % 7 : (x + 2 * y) % 5);
         }
       }
     }
   }
   const bool cb = __ballot(corrupt) != 0;
-  if (cb && lane == 0) atomicOr(&ct->dflags, 1u);
-  // stats (one atomic per wave)
+#pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     moves += (unsigned)__shfl_xor((int)moves, o);
     skips += (unsigned)__shfl_xor((int)skips, o);
   }
-  if (lane == 0 && (moves | skips)) {
-    atomicAdd(&ct->st_moves, (unsigned long long)moves);
-    atomicAdd(&ct->st_skips, (unsigned long long)skips);
+  if (lane == 0) {
+    if (moves) atomicAdd(&s_moves, moves);
+    if (skips) atomicAdd(&s_skips, skips);
+    if (cb) atomicOr(&s_corrupt, 1u);
+  }
+  __syncthreads();
+  // the chunk's queue to its slot range, and its counters
+  const unsigned qn = s_qn;
+  unsigned* qi = reinterpret_cast<unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
+  uint8_t* qc = a.ws + L.col + (size_t)c * kChunk;
+  for (unsigned t = tid; t < qn; t += WAVES * 64) {
+    qi[t] = s_qi[t];
+    qc[t] = s_qc[t];
+  }
+  if (tid == 0) {
+    reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = qn;
+    reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = s_moves;
+    reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = s_skips;
+    dflag[c] = s_corrupt;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Saddle refinement.
 
+struct Pt {
+  int x, y, z;
+};
+__device__ __forceinline__ Pt coords(int i, const Plan& p) {
+  const int t = i / p.nx;
+  return {i - t * p.nx, t % p.ny, t / p.ny};
+}
+
 __device__ int classify_at(const float* fld, int i, int pi, float pv, const Plan& p) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int x = i % nx, t = i / nx, y = t % ny, z = t / ny;
+  const Pt c = coords(i, p);
   const int nxy = nx * ny;
   float nb[6];
   bool av[6];
-  av[0] = x > 0;
-  av[1] = x < nx - 1;
-  av[2] = y > 0;
-  av[3] = y < ny - 1;
-  av[4] = z > 0;
-  av[5] = z < nz - 1;
+  av[0] = c.x > 0;
+  av[1] = c.x < nx - 1;
+  av[2] = c.y > 0;
+  av[3] = c.y < ny - 1;
+  av[4] = c.z > 0;
+  av[5] = c.z < nz - 1;
   const int nbi[6] = {i - 1, i + 1, i - nx, i + nx, i - nxy, i + nxy};
 #pragma unroll
   for (int j = 0; j < 6; ++j) nb[j] = av[j] ? (nbi[j] == pi ? pv : fld[nbi[j]]) : 0.0f;
@@ -1037,7 +1163,7 @@ __device__ int classify_at(const float* fld, int i, int pi, float pv, const Plan
 __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Plan& pl, float* vout) {
   if (classify_at(fld, p, -1, 0.0f, pl) == CLS_SAD) return 1;
   const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
-  const int x = p % nx, t = p / nx, y = t % ny, z = t / ny;
+  const Pt c = coords(p, pl);
   const int r = pl.k / 2, rz = pl.ndim == 3 ? r : 0;
   double num = 0.0, den = 0.0;
   for (int dz = -rz; dz <= rz; ++dz)
@@ -1045,7 +1171,7 @@ __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Pl
       for (int dx = -r; dx <= r; ++dx) {
         const int d2 = dz * dz + dy * dy + dx * dx;
         if (d2 == 0 || d2 > r * r) continue;
-        const int zz = z + dz, yy = y + dy, xx = x + dx;
+        const int zz = c.z + dz, yy = c.y + dy, xx = c.x + dx;
         if (zz < 0 || zz >= nz || yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
         const double wt = (double)pl.w[d2];
         num = num + wt * (double)fld[(zz * ny + yy) * nx + xx];
@@ -1057,7 +1183,7 @@ __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Pl
   if (classify_at(fld, p, p, v, pl) != CLS_SAD) return 0;
   const int nxy = nx * ny;
   const int nbi[6] = {p - 1, p + 1, p - nx, p + nx, p - nxy, p + nxy};
-  const bool av[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < nz - 1};
+  const bool av[6] = {c.x > 0, c.x < nx - 1, c.y > 0, c.y < ny - 1, c.z > 0, c.z < nz - 1};
   for (int j = 0; j < 6; ++j) {
     if (!av[j]) continue;
     const int q = nbi[j];
@@ -1070,10 +1196,140 @@ __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Pl
   return 2;
 }
 
-__device__ __forceinline__ void grid_sync(Ctrl* ct, bool single, unsigned& epoch) {
+__device__ __forceinline__ int colour_of(int i, const Plan& p) {
+  const Pt c = coords(i, p);
+  return p.ndim == 3 ? (int)(((long long)c.x + 2ll * c.y + 3ll * c.z) % 7)
+                     : (int)(((long long)c.x + 2ll * c.y) % 5);
+}
+
+// Offsets through which two queued saddles can influence each other's
+// evaluation: the candidate window (Euclidean radius floor(k/2)) and the
+// cells the acceptance tests classify (L1 distance <= 2).
+__device__ __forceinline__ bool in_reach(int dx, int dy, int dz, int r) {
+  const int d2 = dx * dx + dy * dy + dz * dz;
+  const int l1 = abs(dx) + abs(dy) + abs(dz);
+  return d2 > 0 && (d2 <= r * r || l1 <= 2);
+}
+
+__device__ __forceinline__ bool queued_at(const unsigned long long* bm, int q) {
+  return (bm[q >> 6] >> (q & 63)) & 1ull;
+}
+
+__global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
+  __shared__ Plan s_p;
+  __shared__ unsigned s_mem[kRefineThreads][kClusterMax];
+  __shared__ float s_val[kRefineThreads][kClusterMax];
+  __shared__ uint8_t s_st[kRefineThreads][kClusterMax];
+  __shared__ unsigned s_commits, s_rounds, s_ok;
+  Ctrl* ct = ctrl_of(a.ws);
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_p = ct->plan;
+    s_ok = ct->hflags == 0 && s_p.valid && s_p.topo;
+    s_commits = 0;
+    s_rounds = 0;
+  }
+  __syncthreads();
+  const Plan& pl = s_p;
+  const int c = blockIdx.x;
+  if (!s_ok || c >= pl.nch) return;
+  const uint64_t nb = ((uint64_t)pl.n + kB - 1) / kB;
+  const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
+  const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
+  const unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
+  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
+  const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
+  unsigned* big = reinterpret_cast<unsigned*>(a.ws + L.big);
+  const uint8_t* labels = a.in + pl.s6_off;
+  const int r = pl.k / 2, R = r > 2 ? r : 2, Rz = pl.ndim == 3 ? R : 0;
+  const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+  unsigned my_commits = 0, my_rounds = 0;
+  for (unsigned t = tid; t < cnt; t += kRefineThreads) {
+    const unsigned slot = (unsigned)c * kChunk + t;
+    const int p = (int)idx[slot];
+    unsigned* mem = s_mem[tid];
+    // the connected set of queued saddles around p (bounded)
+    mem[0] = (unsigned)p;
+    int m = 1, head = 0;
+    bool overflow = false;
+    while (head < m && !overflow) {
+      const int cur = (int)mem[head++];
+      const Pt pc = coords(cur, pl);
+      for (int dz = -Rz; dz <= Rz && !overflow; ++dz)
+        for (int dy = -R; dy <= R && !overflow; ++dy)
+          for (int dx = -R; dx <= R; ++dx) {
+            if (!in_reach(dx, dy, dz, r)) continue;
+            const int xx = pc.x + dx, yy = pc.y + dy, zz = pc.z + dz;
+            if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+            const int q = (zz * ny + yy) * nx + xx;
+            if (!queued_at(bm, q)) continue;
+            bool seen = false;
+            for (int j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
+            if (seen) continue;
+            if (m == kClusterMax) {
+              overflow = true;
+              break;
+            }
+            mem[m++] = (unsigned)q;
+          }
+    }
+    if (overflow) {
+      // left to the cooperative tail kernel (the whole cluster goes there:
+      // every member's search overflows the same way)
+      const unsigned pos = atomicAdd(&ct->big_count, 1u);
+      if (pos < (unsigned)pl.nch * kChunk) big[pos] = slot;
+      continue;
+    }
+    unsigned owner = mem[0];
+    for (int j = 1; j < m; ++j) owner = min(owner, mem[j]);
+    if (owner != (unsigned)p) continue;  // another thread replays this cluster
+    // replay the colour-phased rounds on the cluster (Jacobi within a phase)
+    uint8_t* st = s_st[tid];
+    float* val = s_val[tid];
+    for (int j = 0; j < m; ++j) st[j] = 0;
+    int round = 1;
+    for (; round <= pl.max_rounds; ++round) {
+      unsigned commits = 0;
+      for (int cc = 0; cc < pl.ncol; ++cc) {
+        bool any = false;
+        for (int j = 0; j < m; ++j) {
+          if (st[j] == 1 || colour_of((int)mem[j], pl) != cc) continue;
+          float v;
+          const int res = evaluate(a.out, labels, (int)mem[j], pl, &v);
+          if (res == 1) {
+            st[j] = 1;
+          } else if (res == 2) {
+            st[j] = 2;
+            val[j] = v;
+            any = true;
+          }
+        }
+        if (!any) continue;
+        for (int j = 0; j < m; ++j)
+          if (st[j] == 2) {
+            a.out[mem[j]] = val[j];
+            st[j] = 1;
+            ++commits;
+          }
+      }
+      my_commits += commits;
+      if (commits == 0) break;
+    }
+    my_rounds = max(my_rounds, (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds));
+  }
+  if (my_commits) atomicAdd(&s_commits, my_commits);
+  if (my_rounds) atomicMax(&s_rounds, my_rounds);
+  __syncthreads();
+  if (tid == 0 && (s_commits || s_rounds)) {
+    Spread* sp = spread_of(a.ws) + (c % kSpreadLines);
+    if (s_commits) atomicAdd(&sp->commits, s_commits);
+    atomicMax(&sp->rounds, s_rounds);
+  }
+}
+
+__device__ __forceinline__ void grid_sync(Ctrl* ct, unsigned& epoch) {
   __threadfence();
   __syncthreads();
-  if (single) return;
   if (threadIdx.x == 0) {
     ++epoch;
     const unsigned target = epoch * gridDim.x;
@@ -1081,7 +1337,7 @@ __device__ __forceinline__ void grid_sync(Ctrl* ct, bool single, unsigned& epoch
     unsigned spins = 0;
     while (__hip_atomic_load(&ct->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++spins > kSpinLimit) {
-        atomicOr(&ct->timeout, 2u);
+        atomicOr(&ct->timeout, 1u);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
@@ -1090,102 +1346,125 @@ __device__ __forceinline__ void grid_sync(Ctrl* ct, bool single, unsigned& epoch
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void refine_kernel(RefArgs a) {
+// Clusters too large for one thread: the colour-phased rounds with grid
+// barriers (cooperative launch).  Then status and counters.
+__global__ __launch_bounds__(256) void tail_kernel(RefArgs a) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_count, s_flags;
+  __shared__ unsigned s_big, s_ok, s_hf;
+  __shared__ unsigned long long s_sum[3];
+  __shared__ unsigned s_fl;
   Ctrl* ct = ctrl_of(a.ws);
-  if (threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
     s_p = ct->plan;
-    s_count = ct->wl_count;
-    s_flags = ct->dflags;
+    s_hf = ct->hflags;
+    s_ok = s_hf == 0 && s_p.valid;
+    s_big = ct->big_count;
+    s_sum[0] = s_sum[1] = s_sum[2] = 0;
+    s_fl = 0;
   }
   __syncthreads();
   const Plan& pl = s_p;
-  const unsigned count = pl.valid && s_count > (unsigned)pl.n ? (unsigned)pl.n : s_count;
-  const bool ok = s_flags == 0 && pl.valid && pl.topo;
-  const bool single = count <= (unsigned)kSingleMax;
-  const bool part = ok && count > 0 && (!single || blockIdx.x == 0);
+  const bool ok = s_ok != 0;
+  const uint64_t nb = ok ? ((uint64_t)pl.n + kB - 1) / kB : 0;
+  const DecLayout L = dec_layout(nb, ok ? (uint64_t)pl.nch : 0);
   unsigned* rc = reinterpret_cast<unsigned*>(a.ws + kRcOff);
-  if (part) {
-    const uint64_t qoff = shared_off(a.ws_bytes);
-    const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + qoff);
-    const uint8_t* col = a.ws + qoff + 4ull * pl.n;
-    float* pend = reinterpret_cast<float*>(a.ws + qoff + ((5ull * pl.n + 3) & ~3ull));
-    uint8_t* state = reinterpret_cast<uint8_t*>(pend + pl.n);
+  unsigned tail_rounds = 0;
+  const unsigned cap = ok ? (unsigned)pl.nch * kChunk : 0;
+  const unsigned nbig = ok && pl.topo ? (s_big < cap ? s_big : cap) : 0;
+  if (nbig > 0) {
+    const unsigned* bigl = reinterpret_cast<const unsigned*>(a.ws + L.big);
+    const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
+    const uint8_t* col = a.ws + L.col;
+    uint8_t* state = a.ws + L.state;
+    float* pend = reinterpret_cast<float*>(a.ws + L.pend);
     const uint8_t* labels = a.in + pl.s6_off;
-    const unsigned nthr = single ? blockDim.x : gridDim.x * blockDim.x;
-    const unsigned gtid = single ? threadIdx.x : blockIdx.x * blockDim.x + threadIdx.x;
-    for (unsigned t = gtid; t < count; t += nthr) state[t] = 0;
+    const unsigned nthr = gridDim.x * blockDim.x;
+    const unsigned gtid = blockIdx.x * blockDim.x + tid;
+    for (unsigned t = gtid; t < nbig; t += nthr) state[bigl[t]] = 0;
+    if (gtid == 0)
+      for (int r = 1; r <= pl.max_rounds + 1; ++r) rc[r] = 0;
     unsigned epoch = 0;
-    grid_sync(ct, single, epoch);
+    grid_sync(ct, epoch);
     int round = 1;
     for (; round <= pl.max_rounds; ++round) {
       for (int cc = 0; cc < pl.ncol; ++cc) {
-        for (unsigned t = gtid; t < count; t += nthr) {
-          if (state[t] || col[t] != cc) continue;
-          const int p = (int)idx[t];
+        for (unsigned t = gtid; t < nbig; t += nthr) {
+          const unsigned s = bigl[t];
+          if (state[s] || col[s] != cc) continue;
           float v;
-          const int res = evaluate(a.out, labels, p, pl, &v);
+          const int res = evaluate(a.out, labels, (int)idx[s], pl, &v);
           if (res == 1) {
-            state[t] = 1;
+            state[s] = 1;
           } else if (res == 2) {
             if (pl.twostep) {
-              pend[t] = v;
-              state[t] = 2;
+              pend[s] = v;
+              state[s] = 2;
             } else {
-              a.out[p] = v;
-              state[t] = 1;
+              a.out[idx[s]] = v;
+              state[s] = 1;
             }
             atomicAdd(&rc[round], 1u);
           }
         }
-        grid_sync(ct, single, epoch);
+        grid_sync(ct, epoch);
         if (pl.twostep) {
-          for (unsigned t = gtid; t < count; t += nthr)
-            if (state[t] == 2) {
-              a.out[idx[t]] = pend[t];
-              state[t] = 1;
+          for (unsigned t = gtid; t < nbig; t += nthr) {
+            const unsigned s = bigl[t];
+            if (state[s] == 2) {
+              a.out[idx[s]] = pend[s];
+              state[s] = 1;
             }
-          grid_sync(ct, single, epoch);
+          }
+          grid_sync(ct, epoch);
         }
       }
       const unsigned commits = __hip_atomic_load(&rc[round], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
       if (commits == 0) break;
     }
-    if (gtid == 0) ct->rounds_used = (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
+    tail_rounds = (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
   }
-  // the last workgroup to finish records stats and status and resets
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned d = __hip_atomic_fetch_add(&ct->done_ref, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (d == gridDim.x - 1) {
-      __threadfence();
-      const unsigned ru = (ok && count > 0) ? ct->rounds_used : 0;
-      unsigned long long commits = 0;
-      for (unsigned r = 1; r <= ru; ++r) {
-        commits += rc[r];
-        rc[r] = 0;
-      }
-      const unsigned fl = ct->dflags;
-      ct->stats[0] = ru;
-      ct->stats[1] = commits;
-      ct->stats[2] = count;
-      ct->stats[3] = ct->st_moves;
-      ct->stats[4] = ct->st_skips;
-      *a.status = ct->timeout ? TOPOSZP_E_DEVICE
-                  : (fl & 1u) ? TOPOSZP_E_CORRUPT : ((fl & 2u) ? TOPOSZP_E_CAPACITY : TOPOSZP_OK);
-      ct->timeout = 0;
-      ct->dflags = 0;
-      ct->wl_count = 0;
-      ct->bar = 0;
-      ct->rounds_used = 0;
-      ct->st_moves = 0;
-      ct->st_skips = 0;
-      ct->plan.valid = 0;
-      __threadfence();
-      ct->done_ref = 0;
+  if (blockIdx.x != 0) return;
+  // workgroup 0: counters and status
+  unsigned long long q = 0, mv = 0, sk = 0;
+  unsigned fl = 0;
+  if (ok) {
+    const unsigned* cnt = reinterpret_cast<const unsigned*>(a.ws + L.cnt);
+    const unsigned* mo = reinterpret_cast<const unsigned*>(a.ws + L.moves);
+    const unsigned* skp = reinterpret_cast<const unsigned*>(a.ws + L.skips);
+    const unsigned* df = reinterpret_cast<const unsigned*>(a.ws + L.dflag);
+    for (int k = tid; k < pl.nch; k += blockDim.x) {
+      q += cnt[k];
+      mv += mo[k];
+      sk += skp[k];
+      fl |= df[k];
     }
+  }
+  atomicAdd(&s_sum[0], q);
+  atomicAdd(&s_sum[1], mv);
+  atomicAdd(&s_sum[2], sk);
+  if (fl) atomicOr(&s_fl, fl);
+  __syncthreads();
+  if (tid == 0) {
+    const Spread* sp = spread_of(a.ws);
+    unsigned long long commits = 0;
+    unsigned rounds = tail_rounds;
+    for (int k = 0; k < kSpreadLines; ++k) {
+      commits += sp[k].commits;
+      rounds = max(rounds, sp[k].rounds);
+    }
+    for (int r = 1; r <= (int)tail_rounds; ++r) commits += rc[r];
+    if (ok && pl.topo && rounds == 0) rounds = 1;  // a round that found nothing to do
+    ct->stats[0] = ok && pl.topo ? rounds : 0;
+    ct->stats[1] = commits;
+    ct->stats[2] = s_sum[0];
+    ct->stats[3] = s_sum[1];
+    ct->stats[4] = s_sum[2];
+    int status = TOPOSZP_OK;
+    if (ct->timeout) status = TOPOSZP_E_DEVICE;
+    else if (s_hf == 2u) status = TOPOSZP_E_CAPACITY;
+    else if (s_hf != 0u || s_fl) status = TOPOSZP_E_CORRUPT;
+    *a.status = status;
   }
 }
 
@@ -1221,11 +1500,8 @@ int host_geom(uint32_t ndim, const uint64_t* dims, HostGeom* hg) {
 }
 
 size_t ws_need(const HostGeom& hg) {
-  // queue (10 N) or rank staging (56 per block), plus the look-back area
-  const uint64_t stage = 8ull * kMaxWRankBlk * hg.nb, queue = 10ull * (uint64_t)hg.g.n + 64;
-  uint64_t w = kRegionOff + (stage > queue ? stage : queue) + 4096;
-  w += lookback_bytes(2 * w);
-  return (size_t)(w + 255) & ~size_t(255);
+  const uint64_t c = comp_layout(hg.nch).end, d = dec_layout(hg.nb, hg.nch).end;
+  return (size_t)al256(c > d ? c : d);
 }
 
 float host_round_down(double d) {
@@ -1239,7 +1515,7 @@ bool g_timing = false;
 hipEvent_t g_ev[6][2];
 bool g_ev_used[6];
 bool g_ev_init = false;
-int g_coop_grid = 0;
+int g_tail_grid = 0;
 
 void ev_begin(int k, hipStream_t s) {
   if (!g_timing) return;
@@ -1302,7 +1578,6 @@ int toposzp_workspace_init(void* d_ws, size_t ws_bytes, void* stream) {
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(ws_init_kernel, dim3(grid), dim3(256), 0, s, (uint8_t*)d_ws, (uint64_t)ws_bytes);
-  hipLaunchKernelGGL(ws_init_keys_kernel, dim3(1), dim3(1), 0, s, (uint8_t*)d_ws);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
@@ -1316,7 +1591,7 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   int rc = host_geom(ndim, dims, &hg);
   if (rc != TOPOSZP_OK) return rc;
   if (!d_field || !d_ws || !d_out || !d_out_size || !d_status) return TOPOSZP_E_INVALID_ARG;
-  if (((uintptr_t)d_field & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_out & 7) ||
+  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_out & 7) ||
       ((uintptr_t)d_out_size & 7) || ((uintptr_t)d_status & 3))
     return TOPOSZP_E_INVALID_ARG;
   if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != TOPOSZP_EB_ABS && eb_mode != TOPOSZP_EB_REL))
@@ -1329,26 +1604,36 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
 
+  int nrange = (int)((hg.g.n / 4 + 4095) / 4096);
+  if (nrange > kRangeWG) nrange = kRangeWG;
+  if (nrange < 1) nrange = 1;
+  const float e_abs = host_round_down(eb);
+
   EncArgs ea;
   ea.f = d_field;
   ea.out = d_out;
   ea.ws = (uint8_t*)d_ws;
-  ea.ws_bytes = ws_bytes;
   ea.g = hg.g;
   ea.nb = (int)hg.nb;
   ea.nch = (int)hg.nch;
   ea.topo = p.topo;
   ea.eb_mode = eb_mode;
-  ea.rbf_policy = p.rbf_policy;
-  ea.max_rounds = p.max_rounds;
+  ea.nrange = nrange;
   ea.eb = eb;
-  ea.e_abs = host_round_down(eb);
+  ea.e_abs = e_abs;
   seg_layout(hg.nb, p.topo, 0, 0, ea.off, ea.len);
+
+  ScanArgs sa;
+  sa.ws = (uint8_t*)d_ws;
+  sa.nch = ea.nch;
+  sa.eb_mode = eb_mode;
+  sa.nrange = nrange;
+  sa.eb = eb;
+  sa.e_abs = e_abs;
 
   FinArgs fa;
   fa.out = d_out;
   fa.ws = (uint8_t*)d_ws;
-  fa.ws_bytes = ws_bytes;
   fa.out_size = d_out_size;
   fa.status = d_status;
   fa.g = hg.g;
@@ -1360,7 +1645,6 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   fa.rbf_policy = p.rbf_policy;
   fa.max_rounds = p.max_rounds;
   fa.eb = eb;
-  fa.e_abs = ea.e_abs;
   memcpy(fa.off, ea.off, sizeof(ea.off));
   memcpy(fa.len, ea.len, sizeof(ea.len));
   const double sig[3] = {0.5, 0.75, 1.0};
@@ -1369,21 +1653,16 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
 
   for (int k = 0; k < 3; ++k) g_ev_used[k] = false;
   if (eb_mode == TOPOSZP_EB_REL) {
-    unsigned grid = (unsigned)((hg.g.n / 4 + 255) / 256);
-    if (grid > 2048) grid = 2048;
-    if (grid < 1) grid = 1;
     ev_begin(0, s);
-    hipLaunchKernelGGL(range_kernel, dim3(grid), dim3(256), 0, s, d_field, hg.g.n, (uint8_t*)d_ws);
+    hipLaunchKernelGGL(range_kernel, dim3(nrange), dim3(256), 0, s, d_field, hg.g.n, (uint8_t*)d_ws);
     ev_end(0, s);
   }
   ev_begin(1, s);
   hipLaunchKernelGGL(encode_kernel<kEncWaves>, dim3(ea.nch), dim3(kEncWaves * 64), 0, s, ea);
   ev_end(1, s);
-  unsigned fgrid = (unsigned)((kMaxWRankBlk * hg.nb + 255) / 256);
-  if (fgrid > 1024) fgrid = 1024;
-  if (fgrid < 1) fgrid = 1;
   ev_begin(2, s);
-  hipLaunchKernelGGL(finalize_kernel, dim3(fgrid), dim3(256), 0, s, fa);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sa);
+  hipLaunchKernelGGL(finalize_kernel, dim3(ea.nch), dim3(256), 0, s, fa);
   ev_end(2, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
@@ -1393,7 +1672,7 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   if (!d_in || !d_out || !d_ws || !d_status || out_cap_elems < 1) return TOPOSZP_E_INVALID_ARG;
   if (((uintptr_t)d_in & 7) || ((uintptr_t)d_out & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_status & 3))
     return TOPOSZP_E_INVALID_ARG;
-  if (ws_bytes < kRegionOff + 64) return TOPOSZP_E_CAPACITY;
+  if (ws_bytes < kRegionOff + 4096) return TOPOSZP_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   uint64_t cap = out_cap_elems;
   if (cap > (1ull << 31)) cap = (1ull << 31);
@@ -1409,27 +1688,27 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   ev_begin(3, s);
   hipLaunchKernelGGL(decode_kernel<kDecWaves>, dim3((unsigned)nch), dim3(kDecWaves * 64), 0, s, da);
   ev_end(3, s);
-  if (g_coop_grid == 0) {
-    int dev = 0, per = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, refine_kernel, 256, 0) != hipSuccess)
-      return TOPOSZP_E_DEVICE;
-    int g = per * cus;
-    if (g > cus) g = cus;
-    if (g < 1) g = 1;
-    g_coop_grid = g;
-  }
   RefArgs ra;
   ra.in = d_in;
   ra.out = d_out;
   ra.ws = (uint8_t*)d_ws;
-  ra.ws_bytes = ws_bytes;
   ra.status = d_status;
-  void* args[] = {&ra};
+  if (g_tail_grid == 0) {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, tail_kernel, 256, 0) != hipSuccess)
+      return TOPOSZP_E_DEVICE;
+    int g = per * cus;
+    if (g > 64) g = 64;  // few participants keep each grid barrier short
+    if (g < 1) g = 1;
+    g_tail_grid = g;
+  }
   ev_begin(4, s);
-  hipError_t err = hipLaunchCooperativeKernel((const void*)refine_kernel, dim3(g_coop_grid), dim3(256),
-                                              args, 0, s);
+  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)nch), dim3(kRefineThreads), 0, s, ra);
+  void* args[] = {&ra};
+  hipError_t err =
+      hipLaunchCooperativeKernel((const void*)tail_kernel, dim3(g_tail_grid), dim3(256), args, 0, s);
   ev_end(4, s);
   if (err != hipSuccess) return TOPOSZP_E_DEVICE;
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
@@ -1438,11 +1717,11 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
 int toposzp_compress_sync(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode,
                           double eb, const toposzp_params* params, void* d_ws, size_t ws_bytes,
                           uint8_t* d_out, size_t out_cap, uint64_t* h_out_size, void* stream) {
-  // status and size travel through the tail of the workspace's control block
+  // status and size travel through the tail of the workspace's control area
   uint8_t* ws = (uint8_t*)d_ws;
   if (!ws || ws_bytes < kRegionOff) return TOPOSZP_E_INVALID_ARG;
-  uint64_t* d_size = reinterpret_cast<uint64_t*>(ws + kCtrlBytes - 16);
-  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kCtrlBytes - 8);
+  uint64_t* d_size = reinterpret_cast<uint64_t*>(ws + kSpreadOff - 16);
+  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kSpreadOff - 8);
   int rc = toposzp_compress(d_field, ndim, dims, eb_mode, eb, params, d_ws, ws_bytes, d_out, out_cap,
                             d_size, d_stat, stream);
   if (rc != TOPOSZP_OK) return rc;
@@ -1460,7 +1739,7 @@ int toposzp_decompress_sync(const uint8_t* d_in, size_t in_size, float* d_out, s
                             void* d_ws, size_t ws_bytes, void* stream) {
   uint8_t* ws = (uint8_t*)d_ws;
   if (!ws || ws_bytes < kRegionOff) return TOPOSZP_E_INVALID_ARG;
-  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kCtrlBytes - 8);
+  int32_t* d_stat = reinterpret_cast<int32_t*>(ws + kSpreadOff - 8);
   int rc = toposzp_decompress(d_in, in_size, d_out, out_cap_elems, d_ws, ws_bytes, d_stat, stream);
   if (rc != TOPOSZP_OK) return rc;
   int32_t st = 0;
