@@ -24,9 +24,9 @@
 //                    schedule, so an isolated saddle is settled by a single
 //                    evaluation and a small cluster by one thread replaying
 //                    the schedule on its members.
-//   tail_kernel      cooperative: the same schedule with grid barriers for
-//                    the rare clusters too large for one thread; status and
-//                    counters.
+//   tail_kernel      one workgroup: the same schedule with workgroup
+//                    barriers for the rare clusters too large for one
+//                    thread; status and counters.
 //
 // No kernel contends on a single global address; every device wait is
 // bounded.  Readings of points the paper leaves open are stated where used.
@@ -55,18 +55,26 @@ constexpr int kRangeWG = 512;          // max range-pass workgroups
 constexpr int kClusterMax = 32;        // cluster members one thread replays
 constexpr int kRefineThreads = 128;
 constexpr int kSpreadLines = 64;       // counters spread over cache lines
-constexpr unsigned kSpinLimit = 1u << 22;
 enum { S1, S2, S3, S4, S6, R1, R2, R3, R4, X1, X2, S5, R5 };
 enum { CLS_R = 0, CLS_MIN = 1, CLS_SAD = 2, CLS_MAX = 3 };
 
 // ---------------------------------------------------------------------------
-// Workspace layout: control block, spread counters, per-round counters of
-// the cooperative tail, range partials, then a region whose layout depends
-// on the call's field size (each call writes what it reads there).
+// Workspace layout: control block, spread counters, range partials, then a
+// region whose layout depends on the call's field size (each call writes
+// what it reads there).
+
+struct Div {
+  unsigned m;
+  int l;
+};
+struct GeomD {
+  int n, nx, ny, nz, nxy;
+  Div dx, dy;
+};
 
 struct Plan {                 // decode -> refine/tail hand-off
-  int valid, topo, ndim, k, ncol, max_rounds, twostep, nch;
-  int n, nx, ny, nz;
+  int valid, topo, ndim, k, ncol, max_rounds, nch;
+  GeomD g;
   float e;
   float w[10];
   uint64_t s6_off;
@@ -81,8 +89,6 @@ struct Ctrl {
   // decompression
   unsigned hflags;            // header check of this call: 0 good, 1 corrupt, 2 capacity
   unsigned big_count;         // saddles in clusters left to the tail kernel
-  unsigned bar;               // tail grid barrier arrivals
-  unsigned timeout;           // a bounded wait gave up
   unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
   Plan plan;
 };
@@ -93,8 +99,7 @@ struct Spread {               // one cache line each
 };
 
 constexpr size_t kSpreadOff = 1024;
-constexpr size_t kRcOff = kSpreadOff + sizeof(Spread) * kSpreadLines;
-constexpr size_t kPartOff = (kRcOff + 4 * (kMaxRounds + 2) + 255) & ~size_t(255);
+constexpr size_t kPartOff = (kSpreadOff + sizeof(Spread) * kSpreadLines + 255) & ~size_t(255);
 constexpr size_t kRegionOff = (kPartOff + 16 * kRangeWG + 255) & ~size_t(255);
 
 __host__ __device__ constexpr uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -198,17 +203,73 @@ __device__ __forceinline__ int classify6(float a, const float nb[6], const bool 
   return CLS_R;
 }
 
-__device__ __forceinline__ unsigned wave_max_u(unsigned v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o));
-  return v;
+// Division by an invariant 31-bit divisor d (Granlund-Montgomery): with
+// l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32, floor(n / d) =
+// floor(n * m / 2^(31+l)) for every 0 <= n < 2^31.
+__host__ __device__ inline Div make_div(unsigned d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const unsigned long long m = ((1ull << (31 + l)) + d - 1) / d;
+  return {(unsigned)m, l};
 }
+__device__ __forceinline__ int fdiv(int n, Div v) {
+  return v.l == 0 ? n : (int)(__umulhi((unsigned)n, v.m) >> (v.l - 1));
+}
+
+// Grid coordinates of flat index i (x fastest).
+struct Pt {
+  int x, y, z;
+};
+__device__ __forceinline__ Pt coords_of(int i, const GeomD& g) {
+  const int t = fdiv(i, g.dx);
+  const int z = fdiv(t, g.dy);
+  return {i - t * g.nx, t - z * g.ny, z};
+}
+
+// Cross-lane moves on the data-parallel-primitives path (all 64 lanes active):
+// wave_shr:1 (lane i reads lane i-1, lane 0 reads `edge`), wave_shl:1 (lane i
+// reads lane i+1, lane 63 reads `edge`), and row-level patterns.
+__device__ __forceinline__ int dpp_from_prev(int v, int edge) {
+  return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_from_next(int v, int edge) {
+  return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ unsigned wave_max_u(unsigned v) {
+  // within each row of 16: xor 1, xor 2 (quad permutes), rotate 4, rotate 8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+// Inclusive prefix sum over the wave: shifts by 1, 2, 4, 8 within rows of
+// 16, then row 0's total into row 1 (and 2's into 3), then rows 0-1 into 2-3.
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o);
-    if (lane >= o) v = (int)((unsigned)v + (unsigned)t);
-  }
+  (void)lane;
+  unsigned u = (unsigned)v;
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x111, 0xf, 0xf, false);
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x112, 0xf, 0xf, false);
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x114, 0xf, 0xf, false);
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x118, 0xf, 0xf, false);
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x142, 0xa, 0xf, false);
+  u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x143, 0xc, 0xf, false);
+  return (int)u;
+}
+// Lane `l` (uniform) takes the uniform value `v`; other lanes keep `old`.
+__device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v, int l) {
+  return (int)(threadIdx.x & 63) == l ? v : old;
+}
+// OR over each row of 16 lanes, complete in the row's last lane.
+__device__ __forceinline__ unsigned row_or_last(unsigned v) {
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
   return v;
 }
 __device__ __forceinline__ unsigned mbcnt(unsigned long long m) {
@@ -219,25 +280,26 @@ __device__ __forceinline__ unsigned mbcnt(unsigned long long m) {
 // r_0 = 0, r_i = v_i - v_{i-1}; width = bit length of max |r_i|; the sign and
 // each bit plane are one 64-bit ballot.  Planes go to dst[0..w) (LDS).
 template <int MAXW>
-__device__ __forceinline__ int encode_block(int v, int lane, unsigned long long* dst,
+__device__ __forceinline__ int encode_block(int v, int lane, unsigned* dst,
                                             unsigned long long& sign, int& first, bool& over) {
-  const int prev = __shfl_up(v, 1);
-  long long r = (long long)v - (long long)prev;
-  if (lane == 0) r = 0;
+  const int prev = dpp_from_prev(v, v);  // lane 0 sees itself: residual 0
+  const long long r = (long long)v - (long long)prev;
   sign = __ballot(r < 0);
   const unsigned mag = (unsigned)(r < 0 ? -r : r);
   const unsigned mx = wave_max_u(mag);
-  int w = mx ? 32 - __clz((int)mx) : 0;
+  int w = mx ? 32 - __builtin_clz(mx) : 0;
   if (w > MAXW) {
     over = true;
     w = MAXW;
   }
-  unsigned long long mine = 0;
+  // plane j = ballot of bit j; its two halves go to lanes 2j, 2j+1
+  unsigned mine = 0;
   for (int j = 0; j < w; ++j) {
     const unsigned long long pl = __ballot((mag >> j) & 1u);
-    if (lane == j) mine = pl;
+    mine = write_lane(mine, (unsigned)pl, 2 * j);
+    mine = write_lane(mine, (unsigned)(pl >> 32), 2 * j + 1);
   }
-  if (lane < w) dst[lane] = mine;
+  if (lane < 2 * w) dst[lane] = mine;
   first = __builtin_amdgcn_readlane(v, 0);
   return w;
 }
@@ -247,9 +309,11 @@ __device__ __forceinline__ int encode_block(int v, int lane, unsigned long long*
 __device__ __forceinline__ int decode_block(const uint8_t* planes, int w, int first,
                                             unsigned long long sign, int lane) {
   unsigned mag = 0;
+  const unsigned sh = (unsigned)lane & 31u, hi = (unsigned)lane >> 5;
   for (int j = 0; j < w; ++j) {
     const unsigned long long pl = *(const unsigned long long*)(planes + 8 * (size_t)j);
-    mag |= (unsigned)((pl >> lane) & 1ull) << j;
+    const unsigned half = hi ? (unsigned)(pl >> 32) : (unsigned)pl;
+    mag |= ((half >> sh) & 1u) << j;
   }
   int r = ((sign >> lane) & 1ull) ? (int)(0u - mag) : (int)mag;
   if (lane == 0) r = first;
@@ -267,7 +331,7 @@ struct EncArgs {
   const float* f;
   uint8_t* out;
   uint8_t* ws;
-  Geom g;
+  GeomD gd;
   int nb, nch, topo, eb_mode, nrange;
   double eb;
   float e_abs;
@@ -440,8 +504,8 @@ __device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_ab
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   constexpr int BPW = kB / WAVES;  // blocks per wave
-  __shared__ unsigned long long s_pd[kB][kMaxWData];
-  __shared__ unsigned long long s_pr[kB][kMaxWRankBlk];
+  __shared__ unsigned s_pd[kB][2 * kMaxWData];
+  __shared__ unsigned s_pr[kB][2 * kMaxWRankBlk];
   __shared__ int s_wd[kB], s_wr[kB];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1];
   __shared__ float s_e;
@@ -463,9 +527,10 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   const float e = s_e;
   const double ed = (double)e;
   const float inv2e = 1.0f / (2.0f * e);
-  const int n = a.g.n, nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const int nxy = nx * ny;
-  const bool deg[3] = {nx < 2, ny < 2, nz < 2};
+  const GeomD& g = a.gd;
+  const int n = g.n;
+  const bool deg[3] = {g.nx < 2, g.ny < 2, g.nz < 2};
+  const float* __restrict__ f = a.f;
   bool nonfinite = false, qover = false, wover = false;
 
   for (int k = 0; k < BPW; ++k) {
@@ -478,39 +543,48 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
       }
       continue;
     }
-    const int i = b * kB + lane;
+    const int b0 = b * kB;
+    const int i = b0 + lane;
     const bool valid = i < n;
-    const float av = valid ? a.f[i] : 0.0f;
+    const float av = valid ? f[i] : 0.0f;
     nonfinite |= valid && !isfinite(av);
 
     int lab = CLS_R, q = quantize(av, inv2e, ed);
     bool lost = false;
-    if (a.topo && valid) {
-      const int x = i % nx, t = i / nx, y = t % ny, z = t / ny;
-      float nb[6];
-      bool avl[6];
-      avl[0] = x > 0;
-      avl[1] = x < nx - 1;
-      avl[2] = y > 0;
-      avl[3] = y < ny - 1;
-      avl[4] = z > 0;
-      avl[5] = z < nz - 1;
-      nb[0] = avl[0] ? a.f[i - 1] : 0.0f;
-      nb[1] = avl[1] ? a.f[i + 1] : 0.0f;
-      nb[2] = avl[2] ? a.f[i - nx] : 0.0f;
-      nb[3] = avl[3] ? a.f[i + nx] : 0.0f;
-      nb[4] = avl[4] ? a.f[i - nxy] : 0.0f;
-      nb[5] = avl[5] ? a.f[i + nxy] : 0.0f;
-      lab = classify6(av, nb, avl, deg);
-      if (lab != CLS_R) {
-        // flattened by plain SZp iff some face neighbour shares the bin:
-        // -e <= a_n - 2qe < e, exact in double (see quantize)
-        const double c2 = (double)q * (2.0 * ed);
+    if (a.topo) {
+      // x neighbours come from the wave itself; the block's two outer
+      // neighbours are broadcast loads
+      const float el = b0 > 0 ? f[b0 - 1] : 0.0f;
+      const float er = b0 + kB < n ? f[b0 + kB] : 0.0f;
+      const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(el)));
+      const float xr = __int_as_float(dpp_from_next(__float_as_int(av), __float_as_int(er)));
+      if (valid) {
+        const Pt pc = coords_of(i, g);
+        float nb[6];
+        bool avl[6];
+        avl[0] = pc.x > 0;
+        avl[1] = pc.x < g.nx - 1;
+        avl[2] = pc.y > 0;
+        avl[3] = pc.y < g.ny - 1;
+        avl[4] = pc.z > 0;
+        avl[5] = pc.z < g.nz - 1;
+        nb[0] = xl;
+        nb[1] = xr;
+        nb[2] = avl[2] ? f[i - g.nx] : 0.0f;
+        nb[3] = avl[3] ? f[i + g.nx] : 0.0f;
+        nb[4] = avl[4] ? f[i - g.nxy] : 0.0f;
+        nb[5] = avl[5] ? f[i + g.nxy] : 0.0f;
+        lab = classify6(av, nb, avl, deg);
+        if (lab != CLS_R) {
+          // flattened by plain SZp iff some face neighbour shares the bin:
+          // -e <= a_n - 2qe < e, exact in double (see quantize); a higher
+          // neighbour can only share it from above, a lower one from below
+          const double c2 = (double)q * (2.0 * ed);
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          if (!avl[j]) continue;
-          const double d = (double)nb[j] - c2;
-          lost |= (d >= -ed) && (d < ed);
+          for (int j = 0; j < 6; ++j) {
+            const double d = (double)nb[j] - c2;
+            lost |= avl[j] && (nb[j] > av ? (d < ed) : (d >= -ed));
+          }
         }
       }
     }
@@ -537,7 +611,7 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
 
     // the last block is padded with its last value (residual 0)
     if (b == a.nb - 1 && (n & (kB - 1))) {
-      const int last = (n - 1) - b * kB;
+      const int last = (n - 1) - b0;
       const int ql = __builtin_amdgcn_readlane(q, last);
       const int dl = __builtin_amdgcn_readlane(delta, last);
       if (!valid) {
@@ -558,12 +632,8 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
     }
     if (a.topo) {
       // 2-bit labels: point i at byte i/4, bits 2(i%4); 16 points per dword
-      unsigned lv = (unsigned)lab << (2 * (lane & 15));
-      lv |= (unsigned)__shfl_xor((int)lv, 1);
-      lv |= (unsigned)__shfl_xor((int)lv, 2);
-      lv |= (unsigned)__shfl_xor((int)lv, 4);
-      lv |= (unsigned)__shfl_xor((int)lv, 8);
-      if ((lane & 15) == 0)
+      const unsigned lv = row_or_last((unsigned)lab << (2 * (lane & 15)));
+      if ((lane & 15) == 15)
         *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)b + 4 * (lane >> 4)) = lv;
       unsigned long long rsign;
       int rfirst;
@@ -611,26 +681,26 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
 
   // this chunk's planes, compact, to its staging slot (coalesced from LDS)
   {
-    const int totd = s_pfd[kB];
-    uint64_t* dst = reinterpret_cast<uint64_t*>(a.ws + L.stage_d) + (size_t)c * kB * kMaxWData;
+    const int totd = 2 * s_pfd[kB];
+    unsigned* dst = reinterpret_cast<unsigned*>(a.ws + L.stage_d) + (size_t)c * kB * 2 * kMaxWData;
     for (int o = tid; o < totd; o += WAVES * 64) {
-      int lo = 0, hi = kB;  // find lb with s_pfd[lb] <= o < s_pfd[lb+1]
+      int lo = 0, hi = kB;  // find lb with 2 s_pfd[lb] <= o < 2 s_pfd[lb+1]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (s_pfd[mid] <= o) lo = mid; else hi = mid;
+        if (2 * s_pfd[mid] <= o) lo = mid; else hi = mid;
       }
-      dst[o] = s_pd[lo][o - s_pfd[lo]];
+      dst[o] = s_pd[lo][o - 2 * s_pfd[lo]];
     }
     if (a.topo) {
-      const int totr = s_pfr[kB];
-      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * kMaxWRankBlk;
+      const int totr = 2 * s_pfr[kB];
+      unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * kMaxWRankBlk;
       for (int o = tid; o < totr; o += WAVES * 64) {
         int lo = 0, hi = kB;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (s_pfr[mid] <= o) lo = mid; else hi = mid;
+          if (2 * s_pfr[mid] <= o) lo = mid; else hi = mid;
         }
-        rdst[o] = s_pr[lo][o - s_pfr[lo]];
+        rdst[o] = s_pr[lo][o - 2 * s_pfr[lo]];
       }
     }
   }
@@ -953,8 +1023,6 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
     // this call's header verdict and counters for refine/tail
     ct->hflags = h.ok == 1 ? (room ? 0u : 2u) : (h.ok == -1 ? 2u : 1u);
     ct->big_count = 0;
-    ct->bar = 0;
-    ct->timeout = 0;
     Plan& p = ct->plan;
     p.valid = room ? 1 : 0;
     if (room) {
@@ -963,14 +1031,14 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
       p.k = h.k;
       p.ncol = h.ndim == 3 ? 7 : 5;
       p.max_rounds = h.max_rounds;
-      // one commit step per phase when no same-colour point can read
-      // another's update (window radius 1 in 3D, up to 2 in 2D)
-      p.twostep = (h.ndim == 3) ? (h.k > 3) : (h.k > 5);
       p.nch = (int)h.nch;
-      p.n = (int)h.n;
-      p.nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
-      p.ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
-      p.nz = h.ndim == 3 ? (int)h.dims[0] : 1;
+      p.g.n = (int)h.n;
+      p.g.nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
+      p.g.ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
+      p.g.nz = h.ndim == 3 ? (int)h.dims[0] : 1;
+      p.g.nxy = p.g.nx * p.g.ny;
+      p.g.dx = make_div((unsigned)p.g.nx);
+      p.g.dy = make_div((unsigned)p.g.ny);
       p.e = h.e;
       for (int d2 = 0; d2 < 10; ++d2) p.w[d2] = h.w[d2];
       p.s6_off = h.off[S6];
@@ -1128,67 +1196,65 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Saddle refinement.
+// Saddle refinement (specialised on the dimension and kernel size, so the
+// neighbourhoods below are compile-time).
 
-struct Pt {
-  int x, y, z;
-};
-__device__ __forceinline__ Pt coords(int i, const Plan& p) {
-  const int t = i / p.nx;
-  return {i - t * p.nx, t % p.ny, t / p.ny};
-}
-
-__device__ int classify_at(const float* fld, int i, int pi, float pv, const Plan& p) {
-  const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const Pt c = coords(i, p);
-  const int nxy = nx * ny;
+template <int ND>
+__device__ __forceinline__ int classify_at(const float* fld, int i, Pt c, int pi, float pv, const GeomD& g) {
   float nb[6];
   bool av[6];
   av[0] = c.x > 0;
-  av[1] = c.x < nx - 1;
+  av[1] = c.x < g.nx - 1;
   av[2] = c.y > 0;
-  av[3] = c.y < ny - 1;
-  av[4] = c.z > 0;
-  av[5] = c.z < nz - 1;
-  const int nbi[6] = {i - 1, i + 1, i - nx, i + nx, i - nxy, i + nxy};
+  av[3] = c.y < g.ny - 1;
+  av[4] = ND == 3 && c.z > 0;
+  av[5] = ND == 3 && c.z < g.nz - 1;
+  const int nbi[6] = {i - 1, i + 1, i - g.nx, i + g.nx, i - g.nxy, i + g.nxy};
 #pragma unroll
   for (int j = 0; j < 6; ++j) nb[j] = av[j] ? (nbi[j] == pi ? pv : fld[nbi[j]]) : 0.0f;
-  const bool deg[3] = {nx < 2, ny < 2, nz < 2};
+  const bool deg[3] = {g.nx < 2, g.ny < 2, ND != 3 || g.nz < 2};
   const float a = (i == pi) ? pv : fld[i];
   return classify6(a, nb, av, deg);
 }
 
 // Candidate for a flattened saddle p and the acceptance tests:
 // 0 reject, 1 already a saddle, 2 accept (value in *vout).
+template <int ND, int K>
 __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Plan& pl, float* vout) {
-  if (classify_at(fld, p, -1, 0.0f, pl) == CLS_SAD) return 1;
-  const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
-  const Pt c = coords(p, pl);
-  const int r = pl.k / 2, rz = pl.ndim == 3 ? r : 0;
+  const GeomD& g = pl.g;
+  const Pt c = coords_of(p, g);
+  if (classify_at<ND>(fld, p, c, -1, 0.0f, g) == CLS_SAD) return 1;
+  constexpr int r = K / 2, rz = ND == 3 ? r : 0;
   double num = 0.0, den = 0.0;
+#pragma unroll
   for (int dz = -rz; dz <= rz; ++dz)
+#pragma unroll
     for (int dy = -r; dy <= r; ++dy)
+#pragma unroll
       for (int dx = -r; dx <= r; ++dx) {
         const int d2 = dz * dz + dy * dy + dx * dx;
         if (d2 == 0 || d2 > r * r) continue;
         const int zz = c.z + dz, yy = c.y + dy, xx = c.x + dx;
-        if (zz < 0 || zz >= nz || yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
+        if (zz < 0 || zz >= g.nz || yy < 0 || yy >= g.ny || xx < 0 || xx >= g.nx) continue;
         const double wt = (double)pl.w[d2];
-        num = num + wt * (double)fld[(zz * ny + yy) * nx + xx];
+        num = num + wt * (double)fld[p + dz * g.nxy + dy * g.nx + dx];
         den = den + wt;
       }
   if (den == 0.0) return 0;
   const float v = (float)(num / den);
   if (!(fabs((double)v - (double)fld[p]) <= (double)pl.e)) return 0;
-  if (classify_at(fld, p, p, v, pl) != CLS_SAD) return 0;
-  const int nxy = nx * ny;
-  const int nbi[6] = {p - 1, p + 1, p - nx, p + nx, p - nxy, p + nxy};
-  const bool av[6] = {c.x > 0, c.x < nx - 1, c.y > 0, c.y < ny - 1, c.z > 0, c.z < nz - 1};
+  if (classify_at<ND>(fld, p, c, p, v, g) != CLS_SAD) return 0;
+  const int nbi[6] = {p - 1, p + 1, p - g.nx, p + g.nx, p - g.nxy, p + g.nxy};
+  const Pt nbc[6] = {{c.x - 1, c.y, c.z}, {c.x + 1, c.y, c.z}, {c.x, c.y - 1, c.z},
+                     {c.x, c.y + 1, c.z}, {c.x, c.y, c.z - 1}, {c.x, c.y, c.z + 1}};
+  const bool av[6] = {c.x > 0, c.x < g.nx - 1, c.y > 0, c.y < g.ny - 1,
+                      ND == 3 && c.z > 0, ND == 3 && c.z < g.nz - 1};
+#pragma unroll
   for (int j = 0; j < 6; ++j) {
     if (!av[j]) continue;
     const int q = nbi[j];
-    const int before = classify_at(fld, q, -1, 0.0f, pl);
-    const int after = classify_at(fld, q, p, v, pl);
+    const int before = classify_at<ND>(fld, q, nbc[j], -1, 0.0f, g);
+    const int after = classify_at<ND>(fld, q, nbc[j], p, v, g);
     const int lab = (labels[q >> 2] >> (2 * (q & 3))) & 3;
     if (after != before && !(before == CLS_R && after == lab)) return 0;
   }
@@ -1196,23 +1262,111 @@ __device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Pl
   return 2;
 }
 
-__device__ __forceinline__ int colour_of(int i, const Plan& p) {
-  const Pt c = coords(i, p);
-  return p.ndim == 3 ? (int)(((long long)c.x + 2ll * c.y + 3ll * c.z) % 7)
-                     : (int)(((long long)c.x + 2ll * c.y) % 5);
+__device__ __forceinline__ int colour_of(int i, const GeomD& g, int ndim) {
+  const Pt c = coords_of(i, g);
+  return ndim == 3 ? (int)(((unsigned)c.x + 2u * (unsigned)c.y + 3u * (unsigned)c.z) % 7u)
+                   : (int)(((unsigned)c.x + 2u * (unsigned)c.y) % 5u);
 }
 
 // Offsets through which two queued saddles can influence each other's
 // evaluation: the candidate window (Euclidean radius floor(k/2)) and the
 // cells the acceptance tests classify (L1 distance <= 2).
-__device__ __forceinline__ bool in_reach(int dx, int dy, int dz, int r) {
-  const int d2 = dx * dx + dy * dy + dz * dz;
-  const int l1 = abs(dx) + abs(dy) + abs(dz);
-  return d2 > 0 && (d2 <= r * r || l1 <= 2);
+__host__ __device__ constexpr bool in_reach(int dx, int dy, int dz, int r) {
+  return (dx * dx + dy * dy + dz * dz) > 0 &&
+         ((dx * dx + dy * dy + dz * dz) <= r * r ||
+          (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz) <= 2);
 }
 
-__device__ __forceinline__ bool queued_at(const unsigned long long* bm, int q) {
-  return (bm[q >> 6] >> (q & 63)) & 1ull;
+// Queued saddles within reach of cur, appended to mem[m..] if new; returns
+// false when the list would exceed kClusterMax.
+template <int ND, int K>
+__device__ __forceinline__ bool gather(const unsigned long long* bm, int cur, const GeomD& g, unsigned* mem,
+                                       int& m) {
+  constexpr int r = K / 2, R = r > 2 ? r : 2, RZ = ND == 3 ? R : 0;
+  const Pt c = coords_of(cur, g);
+#pragma unroll
+  for (int dz = -RZ; dz <= RZ; ++dz)
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        if (!in_reach(dx, dy, dz, r)) continue;
+        const int xx = c.x + dx, yy = c.y + dy, zz = c.z + dz;
+        const bool in = xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz;
+        const int q = cur + dz * g.nxy + dy * g.nx + dx;
+        const unsigned long long word = in ? bm[q >> 6] : 0ull;
+        if (!((word >> (q & 63)) & 1ull)) continue;
+        bool seen = false;
+        for (int j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
+        if (seen) continue;
+        if (m == kClusterMax) return false;
+        mem[m++] = (unsigned)q;
+      }
+  return true;
+}
+
+template <int ND, int K>
+__device__ void refine_chunk(const RefArgs& a, const Plan& pl, unsigned* mem, float* val, uint8_t* st,
+                             unsigned& my_commits, unsigned& my_rounds) {
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const uint64_t nb = ((uint64_t)pl.g.n + kB - 1) / kB;
+  const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
+  const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
+  const unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
+  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
+  const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
+  unsigned* big = reinterpret_cast<unsigned*>(a.ws + L.big);
+  const uint8_t* labels = a.in + pl.s6_off;
+  for (unsigned t = tid; t < cnt; t += kRefineThreads) {
+    const unsigned slot = (unsigned)c * kChunk + t;
+    const int p = (int)idx[slot];
+    // the connected set of queued saddles around p (bounded)
+    mem[0] = (unsigned)p;
+    int m = 1, head = 0;
+    bool fits = true;
+    while (head < m && fits) fits = gather<ND, K>(bm, (int)mem[head++], pl.g, mem, m);
+    if (!fits) {
+      // left to the tail kernel (every member's search overflows the same way)
+      const unsigned pos = atomicAdd(&ctrl_of(a.ws)->big_count, 1u);
+      if (pos < (unsigned)pl.nch * kChunk) big[pos] = slot;
+      continue;
+    }
+    unsigned owner = mem[0];
+    for (int j = 1; j < m; ++j) owner = min(owner, mem[j]);
+    if (owner != (unsigned)p) continue;  // another thread replays this cluster
+    // replay the colour-phased rounds on the cluster (Jacobi within a phase)
+    for (int j = 0; j < m; ++j) st[j] = (uint8_t)(colour_of((int)mem[j], pl.g, ND) << 2);
+    int round = 1;
+    for (; round <= pl.max_rounds; ++round) {
+      unsigned commits = 0;
+      for (int cc = 0; cc < pl.ncol; ++cc) {
+        bool any = false;
+        for (int j = 0; j < m; ++j) {
+          if ((st[j] & 3) == 1 || (st[j] >> 2) != cc) continue;
+          float v;
+          const int res = evaluate<ND, K>(a.out, labels, (int)mem[j], pl, &v);
+          if (res == 1) {
+            st[j] = (uint8_t)((st[j] & ~3) | 1);
+          } else if (res == 2) {
+            st[j] = (uint8_t)((st[j] & ~3) | 2);
+            val[j] = v;
+            any = true;
+          }
+        }
+        if (!any) continue;
+        for (int j = 0; j < m; ++j)
+          if ((st[j] & 3) == 2) {
+            a.out[mem[j]] = val[j];
+            st[j] = (uint8_t)((st[j] & ~3) | 1);
+            ++commits;
+          }
+      }
+      my_commits += commits;
+      if (commits == 0) break;
+    }
+    my_rounds = max(my_rounds, (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds));
+  }
 }
 
 __global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
@@ -1233,89 +1387,17 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
   const Plan& pl = s_p;
   const int c = blockIdx.x;
   if (!s_ok || c >= pl.nch) return;
-  const uint64_t nb = ((uint64_t)pl.n + kB - 1) / kB;
-  const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
-  const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
-  const unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
-  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
-  const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
-  unsigned* big = reinterpret_cast<unsigned*>(a.ws + L.big);
-  const uint8_t* labels = a.in + pl.s6_off;
-  const int r = pl.k / 2, R = r > 2 ? r : 2, Rz = pl.ndim == 3 ? R : 0;
-  const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
   unsigned my_commits = 0, my_rounds = 0;
-  for (unsigned t = tid; t < cnt; t += kRefineThreads) {
-    const unsigned slot = (unsigned)c * kChunk + t;
-    const int p = (int)idx[slot];
-    unsigned* mem = s_mem[tid];
-    // the connected set of queued saddles around p (bounded)
-    mem[0] = (unsigned)p;
-    int m = 1, head = 0;
-    bool overflow = false;
-    while (head < m && !overflow) {
-      const int cur = (int)mem[head++];
-      const Pt pc = coords(cur, pl);
-      for (int dz = -Rz; dz <= Rz && !overflow; ++dz)
-        for (int dy = -R; dy <= R && !overflow; ++dy)
-          for (int dx = -R; dx <= R; ++dx) {
-            if (!in_reach(dx, dy, dz, r)) continue;
-            const int xx = pc.x + dx, yy = pc.y + dy, zz = pc.z + dz;
-            if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-            const int q = (zz * ny + yy) * nx + xx;
-            if (!queued_at(bm, q)) continue;
-            bool seen = false;
-            for (int j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
-            if (seen) continue;
-            if (m == kClusterMax) {
-              overflow = true;
-              break;
-            }
-            mem[m++] = (unsigned)q;
-          }
-    }
-    if (overflow) {
-      // left to the cooperative tail kernel (the whole cluster goes there:
-      // every member's search overflows the same way)
-      const unsigned pos = atomicAdd(&ct->big_count, 1u);
-      if (pos < (unsigned)pl.nch * kChunk) big[pos] = slot;
-      continue;
-    }
-    unsigned owner = mem[0];
-    for (int j = 1; j < m; ++j) owner = min(owner, mem[j]);
-    if (owner != (unsigned)p) continue;  // another thread replays this cluster
-    // replay the colour-phased rounds on the cluster (Jacobi within a phase)
-    uint8_t* st = s_st[tid];
-    float* val = s_val[tid];
-    for (int j = 0; j < m; ++j) st[j] = 0;
-    int round = 1;
-    for (; round <= pl.max_rounds; ++round) {
-      unsigned commits = 0;
-      for (int cc = 0; cc < pl.ncol; ++cc) {
-        bool any = false;
-        for (int j = 0; j < m; ++j) {
-          if (st[j] == 1 || colour_of((int)mem[j], pl) != cc) continue;
-          float v;
-          const int res = evaluate(a.out, labels, (int)mem[j], pl, &v);
-          if (res == 1) {
-            st[j] = 1;
-          } else if (res == 2) {
-            st[j] = 2;
-            val[j] = v;
-            any = true;
-          }
-        }
-        if (!any) continue;
-        for (int j = 0; j < m; ++j)
-          if (st[j] == 2) {
-            a.out[mem[j]] = val[j];
-            st[j] = 1;
-            ++commits;
-          }
-      }
-      my_commits += commits;
-      if (commits == 0) break;
-    }
-    my_rounds = max(my_rounds, (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds));
+  unsigned* mem = s_mem[tid];
+  float* val = s_val[tid];
+  uint8_t* st = s_st[tid];
+  switch (pl.ndim * 8 + pl.k) {
+    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    default: refine_chunk<3, 7>(a, pl, mem, val, st, my_commits, my_rounds); break;
   }
   if (my_commits) atomicAdd(&s_commits, my_commits);
   if (my_rounds) atomicMax(&s_rounds, my_rounds);
@@ -1327,28 +1409,62 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
   }
 }
 
-__device__ __forceinline__ void grid_sync(Ctrl* ct, unsigned& epoch) {
-  __threadfence();
+// Clusters too large for one thread: the colour-phased rounds by one
+// workgroup with workgroup barriers (rare).  Then status and counters.
+template <int ND, int K>
+__device__ unsigned tail_rounds(const RefArgs& a, const Plan& pl, const DecLayout& L, unsigned nbig) {
+  __shared__ unsigned s_commits;
+  const unsigned* bigl = reinterpret_cast<const unsigned*>(a.ws + L.big);
+  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
+  const uint8_t* col = a.ws + L.col;
+  uint8_t* state = a.ws + L.state;
+  float* pend = reinterpret_cast<float*>(a.ws + L.pend);
+  const uint8_t* labels = a.in + pl.s6_off;
+  const unsigned tid = threadIdx.x, nthr = blockDim.x;
+  for (unsigned t = tid; t < nbig; t += nthr) state[bigl[t]] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ++epoch;
-    const unsigned target = epoch * gridDim.x;
-    __hip_atomic_fetch_add(&ct->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (__hip_atomic_load(&ct->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++spins > kSpinLimit) {
-        atomicOr(&ct->timeout, 1u);
-        break;
+  int round = 1;
+  unsigned total = 0;
+  for (; round <= pl.max_rounds; ++round) {
+    if (tid == 0) s_commits = 0;
+    __syncthreads();
+    for (int cc = 0; cc < pl.ncol; ++cc) {
+      // Jacobi within the phase: evaluate every candidate, then commit
+      for (unsigned t = tid; t < nbig; t += nthr) {
+        const unsigned s = bigl[t];
+        if (state[s] || col[s] != cc) continue;
+        float v;
+        const int res = evaluate<ND, K>(a.out, labels, (int)idx[s], pl, &v);
+        if (res == 1) {
+          state[s] = 1;
+        } else if (res == 2) {
+          pend[s] = v;
+          state[s] = 2;
+          atomicAdd(&s_commits, 1u);
+        }
       }
-      __builtin_amdgcn_s_sleep(2);
+      __threadfence_block();
+      __syncthreads();
+      for (unsigned t = tid; t < nbig; t += nthr) {
+        const unsigned s = bigl[t];
+        if (state[s] == 2) {
+          a.out[idx[s]] = pend[s];
+          state[s] = 1;
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
     }
+    const unsigned commits = s_commits;
+    __syncthreads();
+    total += commits;
+    if (commits == 0) break;
   }
-  __syncthreads();
+  if (tid == 0) ctrl_of(a.ws)->stats[1] = total;
+  return (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
 }
 
-// Clusters too large for one thread: the colour-phased rounds with grid
-// barriers (cooperative launch).  Then status and counters.
-__global__ __launch_bounds__(256) void tail_kernel(RefArgs a) {
+__global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
   __shared__ Plan s_p;
   __shared__ unsigned s_big, s_ok, s_hf;
   __shared__ unsigned long long s_sum[3];
@@ -1362,70 +1478,27 @@ __global__ __launch_bounds__(256) void tail_kernel(RefArgs a) {
     s_big = ct->big_count;
     s_sum[0] = s_sum[1] = s_sum[2] = 0;
     s_fl = 0;
+    ct->stats[1] = 0;
   }
   __syncthreads();
   const Plan& pl = s_p;
   const bool ok = s_ok != 0;
-  const uint64_t nb = ok ? ((uint64_t)pl.n + kB - 1) / kB : 0;
+  const uint64_t nb = ok ? ((uint64_t)pl.g.n + kB - 1) / kB : 0;
   const DecLayout L = dec_layout(nb, ok ? (uint64_t)pl.nch : 0);
-  unsigned* rc = reinterpret_cast<unsigned*>(a.ws + kRcOff);
-  unsigned tail_rounds = 0;
   const unsigned cap = ok ? (unsigned)pl.nch * kChunk : 0;
   const unsigned nbig = ok && pl.topo ? (s_big < cap ? s_big : cap) : 0;
+  unsigned trounds = 0;
   if (nbig > 0) {
-    const unsigned* bigl = reinterpret_cast<const unsigned*>(a.ws + L.big);
-    const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
-    const uint8_t* col = a.ws + L.col;
-    uint8_t* state = a.ws + L.state;
-    float* pend = reinterpret_cast<float*>(a.ws + L.pend);
-    const uint8_t* labels = a.in + pl.s6_off;
-    const unsigned nthr = gridDim.x * blockDim.x;
-    const unsigned gtid = blockIdx.x * blockDim.x + tid;
-    for (unsigned t = gtid; t < nbig; t += nthr) state[bigl[t]] = 0;
-    if (gtid == 0)
-      for (int r = 1; r <= pl.max_rounds + 1; ++r) rc[r] = 0;
-    unsigned epoch = 0;
-    grid_sync(ct, epoch);
-    int round = 1;
-    for (; round <= pl.max_rounds; ++round) {
-      for (int cc = 0; cc < pl.ncol; ++cc) {
-        for (unsigned t = gtid; t < nbig; t += nthr) {
-          const unsigned s = bigl[t];
-          if (state[s] || col[s] != cc) continue;
-          float v;
-          const int res = evaluate(a.out, labels, (int)idx[s], pl, &v);
-          if (res == 1) {
-            state[s] = 1;
-          } else if (res == 2) {
-            if (pl.twostep) {
-              pend[s] = v;
-              state[s] = 2;
-            } else {
-              a.out[idx[s]] = v;
-              state[s] = 1;
-            }
-            atomicAdd(&rc[round], 1u);
-          }
-        }
-        grid_sync(ct, epoch);
-        if (pl.twostep) {
-          for (unsigned t = gtid; t < nbig; t += nthr) {
-            const unsigned s = bigl[t];
-            if (state[s] == 2) {
-              a.out[idx[s]] = pend[s];
-              state[s] = 1;
-            }
-          }
-          grid_sync(ct, epoch);
-        }
-      }
-      const unsigned commits = __hip_atomic_load(&rc[round], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      if (commits == 0) break;
+    switch (pl.ndim * 8 + pl.k) {
+      case 2 * 8 + 3: trounds = tail_rounds<2, 3>(a, pl, L, nbig); break;
+      case 2 * 8 + 5: trounds = tail_rounds<2, 5>(a, pl, L, nbig); break;
+      case 2 * 8 + 7: trounds = tail_rounds<2, 7>(a, pl, L, nbig); break;
+      case 3 * 8 + 3: trounds = tail_rounds<3, 3>(a, pl, L, nbig); break;
+      case 3 * 8 + 5: trounds = tail_rounds<3, 5>(a, pl, L, nbig); break;
+      default: trounds = tail_rounds<3, 7>(a, pl, L, nbig); break;
     }
-    tail_rounds = (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
   }
-  if (blockIdx.x != 0) return;
-  // workgroup 0: counters and status
+  __syncthreads();
   unsigned long long q = 0, mv = 0, sk = 0;
   unsigned fl = 0;
   if (ok) {
@@ -1447,13 +1520,12 @@ __global__ __launch_bounds__(256) void tail_kernel(RefArgs a) {
   __syncthreads();
   if (tid == 0) {
     const Spread* sp = spread_of(a.ws);
-    unsigned long long commits = 0;
-    unsigned rounds = tail_rounds;
+    unsigned long long commits = ct->stats[1];
+    unsigned rounds = trounds;
     for (int k = 0; k < kSpreadLines; ++k) {
       commits += sp[k].commits;
       rounds = max(rounds, sp[k].rounds);
     }
-    for (int r = 1; r <= (int)tail_rounds; ++r) commits += rc[r];
     if (ok && pl.topo && rounds == 0) rounds = 1;  // a round that found nothing to do
     ct->stats[0] = ok && pl.topo ? rounds : 0;
     ct->stats[1] = commits;
@@ -1461,8 +1533,7 @@ __global__ __launch_bounds__(256) void tail_kernel(RefArgs a) {
     ct->stats[3] = s_sum[1];
     ct->stats[4] = s_sum[2];
     int status = TOPOSZP_OK;
-    if (ct->timeout) status = TOPOSZP_E_DEVICE;
-    else if (s_hf == 2u) status = TOPOSZP_E_CAPACITY;
+    if (s_hf == 2u) status = TOPOSZP_E_CAPACITY;
     else if (s_hf != 0u || s_fl) status = TOPOSZP_E_CORRUPT;
     *a.status = status;
   }
@@ -1515,7 +1586,6 @@ bool g_timing = false;
 hipEvent_t g_ev[6][2];
 bool g_ev_used[6];
 bool g_ev_init = false;
-int g_tail_grid = 0;
 
 void ev_begin(int k, hipStream_t s) {
   if (!g_timing) return;
@@ -1613,7 +1683,13 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   ea.f = d_field;
   ea.out = d_out;
   ea.ws = (uint8_t*)d_ws;
-  ea.g = hg.g;
+  ea.gd.n = hg.g.n;
+  ea.gd.nx = hg.g.nx;
+  ea.gd.ny = hg.g.ny;
+  ea.gd.nz = hg.g.nz;
+  ea.gd.nxy = hg.g.nx * hg.g.ny;
+  ea.gd.dx = make_div((unsigned)hg.g.nx);
+  ea.gd.dy = make_div((unsigned)hg.g.ny);
   ea.nb = (int)hg.nb;
   ea.nch = (int)hg.nch;
   ea.topo = p.topo;
@@ -1693,24 +1769,10 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   ra.out = d_out;
   ra.ws = (uint8_t*)d_ws;
   ra.status = d_status;
-  if (g_tail_grid == 0) {
-    int dev = 0, per = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, tail_kernel, 256, 0) != hipSuccess)
-      return TOPOSZP_E_DEVICE;
-    int g = per * cus;
-    if (g > 64) g = 64;  // few participants keep each grid barrier short
-    if (g < 1) g = 1;
-    g_tail_grid = g;
-  }
   ev_begin(4, s);
   hipLaunchKernelGGL(refine_kernel, dim3((unsigned)nch), dim3(kRefineThreads), 0, s, ra);
-  void* args[] = {&ra};
-  hipError_t err =
-      hipLaunchCooperativeKernel((const void*)tail_kernel, dim3(g_tail_grid), dim3(256), args, 0, s);
+  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, ra);
   ev_end(4, s);
-  if (err != hipSuccess) return TOPOSZP_E_DEVICE;
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
