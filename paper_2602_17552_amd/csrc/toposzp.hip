@@ -33,11 +33,16 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
 #include "toposzp.h"
+
+// The compiler's lane-write intrinsic (v_writelane_b32): lane `l` (uniform)
+// of `old` takes the uniform value `v`.
+__device__ int llvm_writelane(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
 
 namespace {
 
@@ -51,9 +56,9 @@ constexpr int kMaxWRankAny = 31;       // field-scope ranks lie in [0, N]
 constexpr int kNSeg = 13;
 constexpr int kMaxRounds = 65535;
 constexpr int kChunk = kB * kB;        // points per chunk
-constexpr int kRangeWG = 512;          // max range-pass workgroups
-constexpr int kClusterMax = 32;        // cluster members one thread replays
-constexpr int kRefineThreads = 128;
+constexpr int kRangeWG = 1024;         // max range-pass workgroups
+constexpr int kRangeVec = 8;           // float4 loads per thread per pass
+constexpr int kFuseMax = 4096;         // chunk counts whose scan finalize does itself
 constexpr int kSpreadLines = 64;       // counters spread over cache lines
 enum { S1, S2, S3, S4, S6, R1, R2, R3, R4, X1, X2, S5, R5 };
 enum { CLS_R = 0, CLS_MIN = 1, CLS_SAD = 2, CLS_MAX = 3 };
@@ -88,7 +93,7 @@ struct Ctrl {
   double eps;
   // decompression
   unsigned hflags;            // header check of this call: 0 good, 1 corrupt, 2 capacity
-  unsigned big_count;         // saddles in clusters left to the tail kernel
+  unsigned big;               // a cluster too large for a wave: whole-field replay
   unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
   Plan plan;
 };
@@ -119,7 +124,7 @@ __host__ __device__ inline CompLayout comp_layout(uint64_t nch) {
 }
 
 struct DecLayout {
-  uint64_t cnt, moves, skips, dflag, bitmap, idx, col, state, pend, big, end;
+  uint64_t cnt, moves, skips, dflag, bitmap, idx, state, pend, end;
 };
 __host__ __device__ inline DecLayout dec_layout(uint64_t nb, uint64_t nch) {
   DecLayout L;
@@ -130,11 +135,9 @@ __host__ __device__ inline DecLayout dec_layout(uint64_t nb, uint64_t nch) {
   L.dflag = L.skips + 4 * nch;
   L.bitmap = al256(L.dflag + 4 * nch);
   L.idx = al256(L.bitmap + 8 * nb);
-  L.col = al256(L.idx + 4 * slots);
-  L.state = al256(L.col + slots);
+  L.state = al256(L.idx + 4 * slots);
   L.pend = al256(L.state + slots);
-  L.big = al256(L.pend + 4 * slots);
-  L.end = al256(L.big + 4 * slots);
+  L.end = al256(L.pend + 4 * slots);
   return L;
 }
 
@@ -174,33 +177,27 @@ __device__ __forceinline__ int quantize(float a, float inv2e, double ed) {
   return q;
 }
 
-// Class from the six face neighbours [x-, x+, y-, y+, z-, z+]; axes of
-// extent 1 carry no neighbours and take no part in the saddle test.
-__device__ __forceinline__ int classify6(float a, const float nb[6], const bool av[6],
-                                         const bool deg[3]) {
-  int navail = 0, up = 0, dn = 0;
-  bool all_gt = true, all_lt = true, pairs_ok = true;
+// Class from the six face neighbours [x-, x+, y-, y+, z-, z+] (Section
+// III-A).  avm: bit j set if neighbour j exists; ndeg: bit 2*axis set for
+// each axis of extent >= 2 (an axis of extent 1 has no neighbours and takes
+// no part in the saddle test).  Minimum: every neighbour higher; maximum:
+// every neighbour lower; saddle: along every axis both neighbours higher or
+// both lower, with at least one axis of each kind.
+__device__ __forceinline__ int classify_bits(float a, const float nb[6], unsigned avm, unsigned ndeg) {
+  unsigned gt = 0, lt = 0;
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    if (deg[ax]) continue;
-    const bool hl = av[2 * ax], hh = av[2 * ax + 1];
-    const bool lg = hl && nb[2 * ax] > a, ll = hl && nb[2 * ax] < a;
-    const bool hg = hh && nb[2 * ax + 1] > a, hs = hh && nb[2 * ax + 1] < a;
-    navail += (int)hl + (int)hh;
-    if (hl && !lg) all_gt = false;
-    if (hl && !ll) all_lt = false;
-    if (hh && !hg) all_gt = false;
-    if (hh && !hs) all_lt = false;
-    if (!(hl && hh)) pairs_ok = false;
-    else if (lg && hg) ++up;
-    else if (ll && hs) ++dn;
-    else pairs_ok = false;
+  for (int j = 0; j < 6; ++j) {
+    gt |= (nb[j] > a ? 1u : 0u) << j;
+    lt |= (nb[j] < a ? 1u : 0u) << j;
   }
-  if (navail == 0) return CLS_R;
-  if (all_gt) return CLS_MIN;
-  if (all_lt) return CLS_MAX;
-  if (pairs_ok && up > 0 && dn > 0) return CLS_SAD;
-  return CLS_R;
+  gt &= avm;
+  lt &= avm;
+  const unsigned bg = gt & (gt >> 1) & 0x15u, bl = lt & (lt >> 1) & 0x15u;
+  int cls = CLS_R;
+  if (((bg | bl) & ndeg) == ndeg && bg != 0 && bl != 0) cls = CLS_SAD;
+  if (avm != 0 && lt == avm) cls = CLS_MAX;
+  if (avm != 0 && gt == avm) cls = CLS_MIN;
+  return cls;
 }
 
 // Division by an invariant 31-bit divisor d (Granlund-Montgomery): with
@@ -272,48 +269,63 @@ __device__ __forceinline__ unsigned row_or_last(unsigned v) {
   v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
   return v;
 }
+// This lane's bit of a uniform lane mask, as a per-lane condition.
+__device__ __forceinline__ bool lane_in(unsigned long long m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 __device__ __forceinline__ unsigned mbcnt(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// Bit length of the largest of the lanes' values (each < 2^31): a binary
+// search with one lane-mask test per step, steps of 2^(S-1) .. 1.
+template <int S>
+__device__ __forceinline__ int wave_bitlen(unsigned v) {
+  int L = 0;
+#pragma unroll
+  for (int s = 1 << (S - 1); s >= 1; s >>= 1)
+    if (__ballot(v >= (1u << (L + s - 1)))) L += s;
+  return L;
+}
+
 // B + LZ + BE of one 64-value block held one value per lane: residuals
 // r_0 = 0, r_i = v_i - v_{i-1}; width = bit length of max |r_i|; the sign and
-// each bit plane are one 64-bit ballot.  Planes go to dst[0..w) (LDS).
-template <int MAXW>
+// each bit plane are one 64-bit lane mask; plane j goes to dst[2j], dst[2j+1]
+// (LDS) through lanes 2j, 2j+1.  S: search steps of the width (2^S > MAXW).
+template <int MAXW, int S>
 __device__ __forceinline__ int encode_block(int v, int lane, unsigned* dst,
                                             unsigned long long& sign, int& first, bool& over) {
   const int prev = dpp_from_prev(v, v);  // lane 0 sees itself: residual 0
-  const long long r = (long long)v - (long long)prev;
+  const int r = v - prev;                // |v| < 2^23: no overflow
   sign = __ballot(r < 0);
   const unsigned mag = (unsigned)(r < 0 ? -r : r);
-  const unsigned mx = wave_max_u(mag);
-  int w = mx ? 32 - __builtin_clz(mx) : 0;
+  int w = wave_bitlen<S>(mag);
   if (w > MAXW) {
     over = true;
     w = MAXW;
   }
-  // plane j = ballot of bit j; its two halves go to lanes 2j, 2j+1
-  unsigned mine = 0;
+  int mine = 0;
   for (int j = 0; j < w; ++j) {
     const unsigned long long pl = __ballot((mag >> j) & 1u);
-    mine = write_lane(mine, (unsigned)pl, 2 * j);
-    mine = write_lane(mine, (unsigned)(pl >> 32), 2 * j + 1);
+    mine = llvm_writelane((int)(unsigned)pl, 2 * j, mine);
+    mine = llvm_writelane((int)(unsigned)(pl >> 32), 2 * j + 1, mine);
   }
-  if (lane < 2 * w) dst[lane] = mine;
-  first = __builtin_amdgcn_readlane(v, 0);
+  if (lane < 2 * w) dst[lane] = (unsigned)mine;
+  first = __builtin_amdgcn_readfirstlane(v);
   return w;
 }
 
-// Inverse: planes (uniform addresses) -> magnitudes -> signed residuals ->
-// in-wave inclusive prefix sum.
-__device__ __forceinline__ int decode_block(const uint8_t* planes, int w, int first,
-                                            unsigned long long sign, int lane) {
+// Inverse: lane j < w loads plane j; each plane is then broadcast with
+// readlane and every lane takes its own bit; signed residuals; in-wave
+// inclusive prefix sum.
+template <typename PlanePtr>
+__device__ __forceinline__ int decode_block(PlanePtr planes, int w, int first, unsigned long long sign,
+                                            int lane) {
+  const unsigned long long mine = lane < w ? planes[lane] : 0ull;
+  const int lo = (int)(unsigned)mine, hi = (int)(unsigned)(mine >> 32);
   unsigned mag = 0;
-  const unsigned sh = (unsigned)lane & 31u, hi = (unsigned)lane >> 5;
   for (int j = 0; j < w; ++j) {
-    const unsigned long long pl = *(const unsigned long long*)(planes + 8 * (size_t)j);
-    const unsigned half = hi ? (unsigned)(pl >> 32) : (unsigned)pl;
-    mag |= ((half >> sh) & 1u) << j;
+    const unsigned long long pj = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(hi, j) << 32) |
+                                  (unsigned)__builtin_amdgcn_readlane(lo, j);
+    mag |= (unsigned)((pj >> lane) & 1ull) << j;
   }
   int r = ((sign >> lane) & 1ull) ? (int)(0u - mag) : (int)mag;
   if (lane == 0) r = first;
@@ -352,8 +364,9 @@ struct FinArgs {
   int32_t* status;
   Geom g;
   uint64_t dims[3];
-  int nb, nch, topo, eb_mode, rbf_policy, max_rounds;
+  int nb, nch, topo, eb_mode, rbf_policy, max_rounds, nrange, fused;
   double eb;
+  float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
   float wtab[3][10];
 };
@@ -423,18 +436,25 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
   float lo = INFINITY, hi = -INFINITY;
   bool bad = false;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int stride = gridDim.x * blockDim.x;
   const int n4 = n / 4;
   const float4* f4 = reinterpret_cast<const float4*>(f);
-  for (int i = blockIdx.x * blockDim.x + tid; i < n4; i += stride) {
-    const float4 v = f4[i];
-    bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
-    lo = fminf(lo, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
-    hi = fmaxf(hi, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+  // kRangeVec float4 per thread in flight at once; clamped indices repeat
+  // the last vector, which changes neither extreme
+  for (int base = blockIdx.x * 256 * kRangeVec; base < n4; base += gridDim.x * 256 * kRangeVec) {
+    float4 v[kRangeVec];
+#pragma unroll
+    for (int t = 0; t < kRangeVec; ++t) v[t] = f4[min(base + t * 256 + tid, n4 - 1)];
+#pragma unroll
+    for (int t = 0; t < kRangeVec; ++t) {
+      bad |= !(fabsf(v[t].x) <= FLT_MAX) || !(fabsf(v[t].y) <= FLT_MAX) || !(fabsf(v[t].z) <= FLT_MAX) ||
+             !(fabsf(v[t].w) <= FLT_MAX);
+      lo = fminf(lo, fminf(fminf(v[t].x, v[t].y), fminf(v[t].z, v[t].w)));
+      hi = fmaxf(hi, fmaxf(fmaxf(v[t].x, v[t].y), fmaxf(v[t].z, v[t].w)));
+    }
   }
-  for (int i = 4 * n4 + blockIdx.x * blockDim.x + tid; i < n; i += stride) {
-    const float v = f[i];
-    bad |= !isfinite(v);
+  if (blockIdx.x == 0 && tid < n - 4 * n4) {
+    const float v = f[4 * n4 + tid];
+    bad |= !(fabsf(v) <= FLT_MAX);
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
   }
@@ -452,16 +472,10 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
   }
   __syncthreads();
   if (tid == 0) {
-    unsigned a = s_lo[0], b = s_hi[0], c = s_bad[0];
-    for (int k = 1; k < (int)(blockDim.x / 64); ++k) {
-      a = min(a, s_lo[k]);
-      b = max(b, s_hi[k]);
-      c |= s_bad[k];
-    }
-    unsigned* p = reinterpret_cast<unsigned*>(ws + kPartOff + 16 * (size_t)blockIdx.x);
-    p[0] = a;
-    p[1] = b;
-    p[2] = c;
+    const uint4 part = {min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3])),
+                        max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3])), s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3],
+                        0u};
+    reinterpret_cast<uint4*>(ws + kPartOff)[blockIdx.x] = part;
   }
 }
 
@@ -470,11 +484,14 @@ __device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_ab
                            int lane, float* e, float* vmin, float* vmax, double* eps, bool* bad) {
   unsigned lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
   if (eb_mode == TOPOSZP_EB_REL) {
-    for (int k = lane; k < nrange; k += 64) {
-      const unsigned* p = reinterpret_cast<const unsigned*>(ws + kPartOff + 16 * (size_t)k);
-      lo = min(lo, p[0]);
-      hi = max(hi, p[1]);
-      nf |= p[2];
+    // every partial load in flight at once (clamped indices repeat one)
+    const uint4* part = reinterpret_cast<const uint4*>(ws + kPartOff);
+#pragma unroll
+    for (int t = 0; t < kRangeWG / 64; ++t) {
+      const uint4 p = part[min(lane + 64 * t, nrange - 1)];
+      lo = min(lo, p.x);
+      hi = max(hi, p.y);
+      nf |= p.z;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -501,18 +518,70 @@ __device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_ab
 // ---------------------------------------------------------------------------
 // Compression.
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
-  constexpr int BPW = kB / WAVES;  // blocks per wave
+// The dispatcher deals workgroups to the eight XCDs in turn (workgroup w
+// runs on XCD w % 8).  Giving each XCD a contiguous range of chunks keeps the
+// rows above and below a chunk in that XCD's L2.  The grid has 8 * per
+// workgroups; those past the last chunk return at once.
+__host__ __device__ inline int xcd_grid(int nch) { return 8 * ((nch + 7) >> 3); }
+__device__ __forceinline__ int xcd_chunk(int w, int nch) { return (w & 7) * ((nch + 7) >> 3) + (w >> 3); }
+
+// Values one block needs: the lane's own, its y/z face neighbours, and in
+// xe the value just before the block (lane 0) or just after it (other
+// lanes; lane 63 uses it), the x neighbours the wave itself lacks.  Every
+// address is clamped into the field, so each load is in bounds and none is
+// conditional (unused values are masked later); keeping the loads
+// unconditional lets the compiler wait for exactly the block in use.
+struct EncIn {
+  float c, ym, yp, zm, zp, xe;
+};
+
+template <int ND>
+__device__ __forceinline__ EncIn enc_fetch(const float* __restrict__ f, int b, int lane, const GeomD& g) {
+  EncIn r;
+  const int n1 = g.n - 1;
+  const int b0 = min(b * kB, n1);
+  const int i = min(b0 + lane, n1);
+  r.c = f[i];
+  r.ym = f[max(i - g.nx, 0)];
+  r.yp = f[min(i + g.nx, n1)];
+  if (ND == 3) {
+    r.zm = f[max(i - g.nxy, 0)];
+    r.zp = f[min(i + g.nxy, n1)];
+  } else {
+    r.zm = r.zp = 0.0f;
+  }
+  r.xe = f[lane == 0 ? max(b0 - 1, 0) : min(b0 + kB, n1)];
+  return r;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
+  constexpr int WAVES = 4, BPW = kB / WAVES;  // blocks per wave
   __shared__ unsigned s_pd[kB][2 * kMaxWData];
   __shared__ unsigned s_pr[kB][2 * kMaxWRankBlk];
+  __shared__ unsigned long long s_sign[kB], s_rsign[kB];
+  __shared__ int s_first[kB], s_rfirst[kB];
+  __shared__ unsigned s_lab[kB * 4];
   __shared__ int s_wd[kB], s_wr[kB];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1];
   __shared__ float s_e;
   __shared__ unsigned s_flags;
 
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c = blockIdx.x;
+  const int c = xcd_chunk(blockIdx.x, a.nch);
+  if (c >= a.nch) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const GeomD& g = a.gd;
+  const float* __restrict__ f = a.f;
+  const bool topo = a.topo != 0;
+  const int bw = c * kB + wv * BPW;  // this wave's first block
+
+  // the first four blocks' loads go out before the bound is known
+  EncIn P0 = enc_fetch<ND>(f, bw + 0, lane, g);
+  EncIn P1 = enc_fetch<ND>(f, bw + 1, lane, g);
+  EncIn P2 = enc_fetch<ND>(f, bw + 2, lane, g);
+  EncIn P3 = enc_fetch<ND>(f, bw + 3, lane, g);
+
   if (wv == 0) {
     float e, vmin, vmax;
     double eps;
@@ -527,94 +596,110 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   const float e = s_e;
   const double ed = (double)e;
   const float inv2e = 1.0f / (2.0f * e);
-  const GeomD& g = a.gd;
   const int n = g.n;
-  const bool deg[3] = {g.nx < 2, g.ny < 2, g.nz < 2};
-  const float* __restrict__ f = a.f;
-  bool nonfinite = false, qover = false, wover = false;
+  const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
+  unsigned long long nfm = 0, qom = 0;  // lanes with a non-finite value, |q| too large
+  bool wover = false;
 
-  for (int k = 0; k < BPW; ++k) {
-    const int lb = wv * BPW + k;
-    const int b = c * kB + lb;
-    if (b >= a.nb) {
+  const unsigned lab_shift = 2u * (unsigned)(lane & 15);
+  auto block = [&](const EncIn& in, int b) {
+    const int lb = b - c * kB;
+    if (b >= a.nb) {  // past the end (last chunk only)
       if (lane == 0) {
         s_wd[lb] = 0;
         s_wr[lb] = 0;
       }
-      continue;
+      if (lane < 4) s_lab[4 * lb + lane] = 0;
+      return;
     }
     const int b0 = b * kB;
     const int i = b0 + lane;
-    const bool valid = i < n;
-    const float av = valid ? f[i] : 0.0f;
-    nonfinite |= valid && !isfinite(av);
-
-    int lab = CLS_R, q = quantize(av, inv2e, ed);
-    bool lost = false;
-    if (a.topo) {
-      // x neighbours come from the wave itself; the block's two outer
-      // neighbours are broadcast loads
-      const float el = b0 > 0 ? f[b0 - 1] : 0.0f;
-      const float er = b0 + kB < n ? f[b0 + kB] : 0.0f;
-      const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(el)));
-      const float xr = __int_as_float(dpp_from_next(__float_as_int(av), __float_as_int(er)));
-      if (valid) {
-        const Pt pc = coords_of(i, g);
-        float nb[6];
-        bool avl[6];
-        avl[0] = pc.x > 0;
-        avl[1] = pc.x < g.nx - 1;
-        avl[2] = pc.y > 0;
-        avl[3] = pc.y < g.ny - 1;
-        avl[4] = pc.z > 0;
-        avl[5] = pc.z < g.nz - 1;
-        nb[0] = xl;
-        nb[1] = xr;
-        nb[2] = avl[2] ? f[i - g.nx] : 0.0f;
-        nb[3] = avl[3] ? f[i + g.nx] : 0.0f;
-        nb[4] = avl[4] ? f[i - g.nxy] : 0.0f;
-        nb[5] = avl[5] ? f[i + g.nxy] : 0.0f;
-        lab = classify6(av, nb, avl, deg);
-        if (lab != CLS_R) {
-          // flattened by plain SZp iff some face neighbour shares the bin:
-          // -e <= a_n - 2qe < e, exact in double (see quantize); a higher
-          // neighbour can only share it from above, a lower one from below
-          const double c2 = (double)q * (2.0 * ed);
+    // lane masks (bit L = lane L): classification, bins and ranks are
+    // decided with one compare per lane and scalar mask algebra
+    const unsigned long long vm = n - b0 >= kB ? ~0ull : ((1ull << (n - b0)) - 1ull);
+    const float av = in.c;
+    nfm |= __ballot(!isfinite(av)) & vm;
+    int q = quantize(av, inv2e, ed);
+    qom |= __ballot((unsigned)(q + kQMax) > 2u * kQMax) & vm;
+    unsigned long long m_min = 0, m_max = 0, m_sad = 0, lostm = 0;
+    if (topo) {
+      const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(in.xe)));
+      const float xr = __int_as_float(dpp_from_next(__float_as_int(av), __float_as_int(in.xe)));
+      const float nb[6] = {xl, xr, in.ym, in.yp, in.zm, in.zp};
+      const Pt pc = coords_of(i, g);
+      unsigned long long am[6];  // neighbour j exists
+      am[0] = __ballot(pc.x > 0) & vm;
+      am[1] = __ballot(pc.x < g.nx - 1) & vm;
+      am[2] = __ballot(pc.y > 0) & vm;
+      am[3] = __ballot(pc.y < g.ny - 1) & vm;
+      am[4] = ND == 3 ? __ballot(pc.z > 0) & vm : 0ull;
+      am[5] = ND == 3 ? __ballot(pc.z < g.nz - 1) & vm : 0ull;
+      unsigned long long gt[6], lt[6], gtr[6];
 #pragma unroll
-          for (int j = 0; j < 6; ++j) {
-            const double d = (double)nb[j] - c2;
-            lost |= avl[j] && (nb[j] > av ? (d < ed) : (d >= -ed));
-          }
-        }
+      for (int j = 0; j < 2 * ND; ++j) {
+        gtr[j] = __ballot(nb[j] > av);
+        gt[j] = gtr[j] & am[j];
+        lt[j] = __ballot(nb[j] < av) & am[j];
       }
+      unsigned long long anyn = 0, notgt = 0, notlt = 0, pairs = vm, anybg = 0, anybl = 0;
+#pragma unroll
+      for (int j = 0; j < 2 * ND; ++j) {
+        anyn |= am[j];
+        notgt |= am[j] & ~gt[j];
+        notlt |= am[j] & ~lt[j];
+      }
+#pragma unroll
+      for (int ax = 0; ax < ND; ++ax) {
+        const unsigned long long bg = gt[2 * ax] & gt[2 * ax + 1], bl = lt[2 * ax] & lt[2 * ax + 1];
+        anybg |= bg;
+        anybl |= bl;
+        if ((ndeg >> (2 * ax)) & 1u) pairs &= bg | bl;
+      }
+      m_min = anyn & ~notgt;
+      m_max = anyn & ~notlt;
+      m_sad = pairs & anybg & anybl;
+      // flattened by plain SZp iff some face neighbour shares the bin:
+      // -e <= a_n - 2qe < e, exact in double (see quantize); a higher
+      // neighbour can only share it from above, a lower one from below
+      const double c2 = (double)q * (2.0 * ed);
+      unsigned long long same = 0;
+#pragma unroll
+      for (int j = 0; j < 2 * ND; ++j) {
+        const double d = (double)nb[j] - c2;
+        same |= am[j] & ((gtr[j] & __ballot(d < ed)) | (~gtr[j] & __ballot(d >= -ed)));
+      }
+      lostm = (m_min | m_max | m_sad) & same;
     }
-    qover |= valid && (q > kQMax || q < -kQMax);
 
     // ranks of flattened extrema among the flattened extrema of the same
-    // class and bin in this block: 1 + number less extreme
+    // class and bin in this block: 1 + number less extreme; a flattened
+    // saddle gets 1
     int delta = 0;
-    if (a.topo) {
-      const bool isext = lost && (lab == CLS_MIN || lab == CLS_MAX);
-      unsigned long long m = __ballot(isext);
-      const int ck = (q << 1) | (lab == CLS_MAX ? 1 : 0);
-      const int ok = (lab == CLS_MAX) ? fkey(av) : -fkey(av);
+    if (topo) {
+      const unsigned long long ext = lostm & (m_min | m_max);
       int cnt = 0;
-      while (m) {
-        const int j = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const int ckj = __builtin_amdgcn_readlane(ck, j);
-        const int okj = __builtin_amdgcn_readlane(ok, j);
-        cnt += (ck == ckj && okj < ok) ? 1 : 0;
+      if (ext) {
+        const bool ismax = lane_in(m_max);
+        const int ck = (q << 1) | (ismax ? 1 : 0);
+        const int ok = ismax ? fkey(av) : -fkey(av);
+        unsigned long long m = ext;
+        while (m) {
+          const int j = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int ckj = __builtin_amdgcn_readlane(ck, j);
+          const int okj = __builtin_amdgcn_readlane(ok, j);
+          cnt += (ck == ckj && okj < ok) ? 1 : 0;
+        }
       }
-      delta = lost ? (lab == CLS_SAD ? 1 : 1 + cnt) : 0;
+      delta = (lane_in(lostm) ? 1 : 0) + (lane_in(ext) ? cnt : 0);
     }
 
     // the last block is padded with its last value (residual 0)
-    if (b == a.nb - 1 && (n & (kB - 1))) {
+    if (vm != ~0ull) {
       const int last = (n - 1) - b0;
       const int ql = __builtin_amdgcn_readlane(q, last);
       const int dl = __builtin_amdgcn_readlane(delta, last);
-      if (!valid) {
+      if (!lane_in(vm)) {
         q = ql;
         delta = dl;
       }
@@ -622,38 +707,72 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
 
     unsigned long long sign;
     int first;
-    const int w = encode_block<kMaxWData>(q, lane, s_pd[lb], sign, first, wover);
-    uint8_t* out = a.out;
+    const int w = encode_block<kMaxWData, 5>(q, lane, s_pd[lb], sign, first, wover);
     if (lane == 0) {
       s_wd[lb] = w;
-      out[a.off[S2] + b] = (uint8_t)w;
-      *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = sign;
-      *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = first;
+      s_sign[lb] = sign;
+      s_first[lb] = first;
     }
-    if (a.topo) {
+    if (topo) {
       // 2-bit labels: point i at byte i/4, bits 2(i%4); 16 points per dword
-      const unsigned lv = row_or_last((unsigned)lab << (2 * (lane & 15)));
-      if ((lane & 15) == 15)
-        *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)b + 4 * (lane >> 4)) = lv;
+      int lab = lane_in(m_min) ? CLS_MIN : CLS_R;
+      lab = lane_in(m_sad) ? CLS_SAD : lab;
+      lab = lane_in(m_max) ? CLS_MAX : lab;
+      const unsigned lv = row_or_last((unsigned)lab << lab_shift);
+      if ((lane & 15) == 15) s_lab[4 * lb + (lane >> 4)] = lv;
       unsigned long long rsign;
       int rfirst;
       bool rover = false;
-      const int wr = encode_block<kMaxWRankBlk>(delta, lane, s_pr[lb], rsign, rfirst, rover);
+      const int wr = encode_block<kMaxWRankBlk, 3>(delta, lane, s_pr[lb], rsign, rfirst, rover);
       if (lane == 0) {
         s_wr[lb] = wr;
-        out[a.off[R2] + b] = (uint8_t)wr;
-        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = rsign;
-        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = rfirst;
+        s_rsign[lb] = rsign;
+        s_rfirst[lb] = rfirst;
       }
     } else if (lane == 0) {
       s_wr[lb] = 0;
     }
+  };
+
+  // four blocks in flight per wave: each buffer is refilled as soon as its
+  // block has been encoded (the last refills repeat the wave's last block)
+  const int blast = bw + BPW - 1;
+  for (int k = 0; k < BPW; k += 4) {
+    block(P0, bw + k);
+    P0 = enc_fetch<ND>(f, min(bw + k + 4, blast), lane, g);
+    block(P1, bw + k + 1);
+    P1 = enc_fetch<ND>(f, min(bw + k + 5, blast), lane, g);
+    block(P2, bw + k + 2);
+    P2 = enc_fetch<ND>(f, min(bw + k + 6, blast), lane, g);
+    block(P3, bw + k + 3);
+    P3 = enc_fetch<ND>(f, min(bw + k + 7, blast), lane, g);
   }
   {
-    const bool nf = __ballot(nonfinite) != 0, qo = __ballot(qover || wover) != 0;
+    const bool nf = nfm != 0, qo = qom != 0 || wover;
     if (lane == 0 && (nf || qo)) atomicOr(&s_flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
   }
   __syncthreads();
+
+  // per-block fixed-size parts, coalesced: widths, signs, first values,
+  // labels, and the same for the ranks
+  uint8_t* out = a.out;
+  {
+    const int lb = tid & 63, part = tid >> 6;
+    const int b = c * kB + lb;
+    if (b < a.nb) {
+      if (part == 0) {
+        out[a.off[S2] + b] = (uint8_t)s_wd[lb];
+        *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = s_sign[lb];
+        *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = s_first[lb];
+      } else if (part == 1 && topo) {
+        out[a.off[R2] + b] = (uint8_t)s_wr[lb];
+        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = s_rsign[lb];
+        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = s_rfirst[lb];
+      }
+    }
+    if (topo && c * kB + (tid >> 2) < a.nb)
+      *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)(c * kB) + 4 * (size_t)tid) = s_lab[tid];
+  }
 
   // chunk: constant-block bitmaps, local prefix of widths, chunk totals
   const CompLayout L = comp_layout((uint64_t)a.nch);
@@ -668,8 +787,8 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
     if (lane == 0) {
       s_pfd[0] = 0;
       s_pfr[0] = 0;
-      *reinterpret_cast<unsigned long long*>(a.out + a.off[S1] + 8 * (size_t)c) = cb;
-      if (a.topo) *reinterpret_cast<unsigned long long*>(a.out + a.off[R1] + 8 * (size_t)c) = cr;
+      *reinterpret_cast<unsigned long long*>(out + a.off[S1] + 8 * (size_t)c) = cb;
+      if (topo) *reinterpret_cast<unsigned long long*>(out + a.off[R1] + 8 * (size_t)c) = cr;
     }
     if (lane == 63) {
       reinterpret_cast<unsigned*>(a.ws + L.tot_d)[c] = (unsigned)sd;
@@ -691,7 +810,7 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
       }
       dst[o] = s_pd[lo][o - 2 * s_pfd[lo]];
     }
-    if (a.topo) {
+    if (topo) {
       const int totr = 2 * s_pfr[kB];
       unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * kMaxWRankBlk;
       for (int o = tid; o < totr; o += WAVES * 64) {
@@ -798,31 +917,112 @@ __device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   __shared__ uint8_t hdr[kHdr];
   __shared__ unsigned s_sa[4], s_sb[4];
-  const Ctrl* ct = ctrl_of(a.ws);
-  const int tid = threadIdx.x;
-  const int c = blockIdx.x;
+  __shared__ unsigned s_red[5][4];
+  __shared__ unsigned s_flags;
+  __shared__ float s_e, s_vmin, s_vmax;
+  __shared__ double s_eps;
+  Ctrl* ct = ctrl_of(a.ws);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c = xcd_chunk(blockIdx.x, a.nch);  // same XCD as the chunk's encode
+  if (c >= a.nch) return;
+  const bool last = c == a.nch - 1;  // writes the header
   const CompLayout L = comp_layout((uint64_t)a.nch);
-  const uint64_t totd = ct->tot_data, totr = a.topo ? ct->tot_rank : 0;
-  const unsigned* pd = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
-  const unsigned* pr = reinterpret_cast<const unsigned*>(a.ws + L.tot_r);
+  const unsigned* td = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
+  const unsigned* tr = reinterpret_cast<const unsigned*>(a.ws + L.tot_r);
+  const unsigned* cf = reinterpret_cast<const unsigned*>(a.ws + L.cflag);
+  uint64_t b0, r0, nd, nr, totd, totr;
+  if (a.fused) {
+    // td/tr hold per-chunk plane counts: every workgroup sums its
+    // predecessors' (its offsets) and everybody's (the rank planes follow
+    // all data planes); the last one also gathers the flags
+    unsigned pd = 0, pr = 0, ad = 0, ar = 0, fl = 0;
+    for (int base = 0; base < a.nch; base += 256 * 8) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = base + t * 256 + tid;
+        const int jj = min(j, a.nch - 1);
+        const unsigned vd = td[jj], vr = tr[jj], vf = last ? cf[jj] : 0u;
+        if (j < a.nch) {
+          ad += vd;
+          ar += vr;
+          fl |= vf;
+          if (j < c) {
+            pd += vd;
+            pr += vr;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      pd += (unsigned)__shfl_xor((int)pd, o);
+      pr += (unsigned)__shfl_xor((int)pr, o);
+      ad += (unsigned)__shfl_xor((int)ad, o);
+      ar += (unsigned)__shfl_xor((int)ar, o);
+      fl |= (unsigned)__shfl_xor((int)fl, o);
+    }
+    if (lane == 0) {
+      s_red[0][wv] = pd;
+      s_red[1][wv] = pr;
+      s_red[2][wv] = ad;
+      s_red[3][wv] = ar;
+      s_red[4][wv] = fl;
+    }
+    if (last && wv == 0) {
+      float e, vmin, vmax;
+      double eps;
+      bool nf;
+      call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
+      if (lane == 0) {
+        s_e = e;
+        s_vmin = vmin;
+        s_vmax = vmax;
+        s_eps = eps;
+        s_flags = (nf ? 1u : 0u) | ((e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u);
+      }
+    }
+    __syncthreads();
+    b0 = (uint64_t)s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+    r0 = (uint64_t)s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+    totd = (uint64_t)s_red[2][0] + s_red[2][1] + s_red[2][2] + s_red[2][3];
+    totr = (uint64_t)s_red[3][0] + s_red[3][1] + s_red[3][2] + s_red[3][3];
+    nd = td[c];
+    nr = tr[c];
+    if (last && tid == 0) s_flags |= s_red[4][0] | s_red[4][1] | s_red[4][2] | s_red[4][3];
+  } else {
+    // td/tr hold exclusive prefixes, the control block the totals
+    totd = ct->tot_data;
+    totr = ct->tot_rank;
+    b0 = td[c];
+    nd = (c + 1 < a.nch ? (uint64_t)td[c + 1] : totd) - b0;
+    r0 = tr[c];
+    nr = (c + 1 < a.nch ? (uint64_t)tr[c + 1] : totr) - r0;
+    if (last && tid == 0) {
+      s_flags = ct->cflags;
+      s_e = ct->e;
+      s_vmin = ct->vmin;
+      s_vmax = ct->vmax;
+      s_eps = ct->eps;
+    }
+  }
+  if (!a.topo) totr = 0;
   {
-    const uint64_t b0 = pd[c], b1 = c + 1 < a.nch ? pd[c + 1] : totd;
     const uint64_t* src = reinterpret_cast<const uint64_t*>(a.ws + L.stage_d) + (size_t)c * kB * kMaxWData;
     uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + b0;
-    for (uint64_t o = tid; o < b1 - b0; o += blockDim.x) dst[o] = src[o];
+    for (uint64_t o = tid; o < nd; o += blockDim.x) dst[o] = src[o];
     if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * b0;
     if (a.topo) {
-      const uint64_t r0 = pr[c], r1 = c + 1 < a.nch ? pr[c + 1] : totr;
       const uint64_t* rsrc =
           reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * kMaxWRankBlk;
       uint64_t* rdst = reinterpret_cast<uint64_t*>(a.out + a.off[S5] + 8 * totd) + r0;
-      for (uint64_t o = tid; o < r1 - r0; o += blockDim.x) rdst[o] = rsrc[o];
+      for (uint64_t o = tid; o < nr; o += blockDim.x) rdst[o] = rsrc[o];
       if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * r0;
     }
   }
-  if (c != 0) return;
+  if (!last) return;
+  __syncthreads();
 
-  const unsigned flags = ct->cflags;
+  const unsigned flags = s_flags;
   int status = TOPOSZP_OK;
   if (flags & 1u) status = TOPOSZP_E_NONFINITE;
   else if (flags & 6u) status = TOPOSZP_E_RANGE;
@@ -849,11 +1049,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     put2(hdr, 54, (uint16_t)a.max_rounds);
     uint64_t u;
     memcpy(&u, &a.eb, 8); put8(hdr, 56, u);
-    memcpy(&u, &ct->eps, 8); put8(hdr, 64, u);
+    memcpy(&u, &s_eps, 8); put8(hdr, 64, u);
     uint32_t v;
-    memcpy(&v, &ct->e, 4); put4(hdr, 72, v);
-    memcpy(&v, &ct->vmin, 4); put4(hdr, 76, v);
-    memcpy(&v, &ct->vmax, 4); put4(hdr, 80, v);
+    memcpy(&v, &s_e, 4); put4(hdr, 72, v);
+    memcpy(&v, &s_vmin, 4); put4(hdr, 76, v);
+    memcpy(&v, &s_vmax, 4); put4(hdr, 80, v);
     memcpy(&v, &sigma, 4); put4(hdr, 84, v);
     for (int d2 = 0; d2 < 10; ++d2) { memcpy(&v, &a.wtab[si][d2], 4); put4(hdr, 88 + 4 * d2, v); }
     put8(hdr, 128, total);
@@ -992,20 +1192,23 @@ __device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_c
   h->ok = (h->n <= out_cap) ? 1 : -1;
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
-  constexpr int BPW = kB / WAVES;
+__global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
+  constexpr int WAVES = 4, BPW = kB / WAVES;
+  constexpr int kRankLds = kB * kMaxWRankBlk;  // rank planes staged when they fit
   __shared__ Hdr s_h;
   __shared__ uint64_t s_hb[kHdr / 8];
+  __shared__ unsigned long long s_pl[kB * kMaxWData], s_rpl[kRankLds];
+  __shared__ unsigned long long s_sign[kB], s_rsign[kB], s_bm[kB];
+  __shared__ int s_first[kB], s_rfirst[kB];
+  __shared__ unsigned s_lab[kB * 4];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1], s_wd[kB], s_wr[kB];
   __shared__ unsigned long long s_xd, s_xr;
   __shared__ int s_bad;
   __shared__ unsigned s_qn, s_moves, s_skips, s_corrupt;
-  __shared__ unsigned s_qi[kChunk];
-  __shared__ uint8_t s_qc[kChunk];
   Ctrl* ct = ctrl_of(a.ws);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int w_id = blockIdx.x;
   if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, reinterpret_cast<uint8_t*>(s_hb), lane);
   if (tid == 0) {
     s_bad = 0;
@@ -1019,10 +1222,10 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
   const uint64_t nb = h.ok == 1 ? h.nb : 0, nch = h.ok == 1 ? h.nch : 0;
   const DecLayout L = dec_layout(nb, nch);
   const bool room = h.ok == 1 && L.end <= a.ws_bytes;
-  if (c == 0 && tid == 0) {
+  if (w_id == 0 && tid == 0) {
     // this call's header verdict and counters for refine/tail
     ct->hflags = h.ok == 1 ? (room ? 0u : 2u) : (h.ok == -1 ? 2u : 1u);
-    ct->big_count = 0;
+    ct->big = 0;
     Plan& p = ct->plan;
     p.valid = room ? 1 : 0;
     if (room) {
@@ -1044,26 +1247,45 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
       p.s6_off = h.off[S6];
     }
   }
-  if (c == 0 && tid < kSpreadLines) {
+  if (w_id == 0 && tid < kSpreadLines) {
     Spread* sp = spread_of(a.ws);
     sp[tid].commits = 0;
     sp[tid].rounds = 0;
     sp[tid].queued = 0;
   }
-  if (!room || (uint64_t)c >= h.nch) return;
+  // the grid is sized for the output capacity; the chunk mapping covers
+  // exactly the stream's own xcd_grid(nch) workgroups
+  if (!room || w_id >= xcd_grid((int)h.nch)) return;
+  const int c = xcd_chunk(w_id, (int)h.nch);
+  if ((uint64_t)c >= h.nch) return;
   const int n = (int)h.n;
-  const int nx = h.ndim == 3 ? (int)h.dims[2] : (int)h.dims[1];
-  const int ny = h.ndim == 3 ? (int)h.dims[1] : (int)h.dims[0];
+  const bool topo = h.topo != 0;
 
-  // this chunk's widths, constant flags and payload offsets
+  // the chunk's fixed-size parts to LDS (every thread), and its widths,
+  // constant flags and payload offsets (wave 0)
+  {
+    const int lb = tid & 63, part = tid >> 6;
+    const uint64_t b = (uint64_t)c * kB + lb;
+    if (b < h.nb) {
+      if (part == 1) {
+        s_sign[lb] = *reinterpret_cast<const unsigned long long*>(a.in + h.off[S3] + 8 * b);
+        s_first[lb] = *reinterpret_cast<const int*>(a.in + h.off[S4] + 4 * b);
+      } else if (part == 2 && topo) {
+        s_rsign[lb] = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R3] + 8 * b);
+        s_rfirst[lb] = *reinterpret_cast<const int*>(a.in + h.off[R4] + 4 * b);
+      }
+    }
+    if (topo && (uint64_t)c * kB + (tid >> 2) < h.nb)
+      s_lab[tid] = *reinterpret_cast<const unsigned*>(a.in + h.off[S6] + 16 * (uint64_t)c * kB + 4 * tid);
+  }
   if (wv == 0) {
     const uint64_t b = (uint64_t)c * kB + lane;
     const bool bv = b < h.nb;
     const int wd = bv ? a.in[h.off[S2] + b] : 0;
-    const int wr = (bv && h.topo) ? a.in[h.off[R2] + b] : 0;
+    const int wr = (bv && topo) ? a.in[h.off[R2] + b] : 0;
     const unsigned long long cb = *reinterpret_cast<const unsigned long long*>(a.in + h.off[S1] + 8 * (uint64_t)c);
     bool bad = bv && (wd > kMaxWData || (int)((cb >> lane) & 1) != (wd == 0));
-    if (h.topo) {
+    if (topo) {
       const unsigned long long cr = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R1] + 8 * (uint64_t)c);
       bad |= bv && (wr > kMaxWRankAny || (int)((cr >> lane) & 1) != (wr == 0));
       bad |= !bv && (((cr >> lane) & 1) != 0);
@@ -1086,7 +1308,7 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
                                : h.len[S5];
       bool b2 = anybad || (c == 0 && xd != 0) || xd > h.len[S5] || totd > h.len[S5] - xd || xd + totd != nxd;
       uint64_t xr = 0;
-      if (h.topo) {
+      if (topo) {
         xr = *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * (uint64_t)c);
         const uint64_t nxr = (uint64_t)c + 1 < h.nch
                                  ? *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * ((uint64_t)c + 1))
@@ -1111,31 +1333,44 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
     if (tid < kB && (uint64_t)c * kB + tid < h.nb) bitmap[(uint64_t)c * kB + tid] = 0;
     return;
   }
+
+  // the chunk's bit planes to LDS (coalesced); rank planes too when they fit
+  const int nd = s_pfd[kB], nr = s_pfr[kB];
+  const bool rank_lds = nr <= kRankLds;
+  {
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(a.in + h.off[S5] + s_xd);
+    for (int o = tid; o < nd; o += WAVES * 64) s_pl[o] = src[o];
+    if (topo && rank_lds) {
+      const unsigned long long* rsrc = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + s_xr);
+      for (int o = tid; o < nr; o += WAVES * 64) s_rpl[o] = rsrc[o];
+    }
+  }
+  __syncthreads();
+
   const double ed = (double)h.e;
   const float two_e = 2.0f * h.e;
   const int dmax = h.scope ? n : kB;
+  const unsigned long long* rglob = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + s_xr);
+  unsigned* qi = reinterpret_cast<unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
   bool corrupt = false;
   unsigned moves = 0, skips = 0;
   for (int k = 0; k < BPW; ++k) {
     const int lb = wv * BPW + k;
     const uint64_t b = (uint64_t)c * kB + lb;
-    if (b >= h.nb) continue;
+    if (b >= h.nb) break;
     const int i = (int)(b * kB) + lane;
     const bool valid = i < n;
-    const int first = *reinterpret_cast<const int*>(a.in + h.off[S4] + 4 * b);
-    const unsigned long long sign = *reinterpret_cast<const unsigned long long*>(a.in + h.off[S3] + 8 * b);
-    const int q = decode_block(a.in + h.off[S5] + s_xd + 8ull * s_pfd[lb], s_wd[lb], first, sign, lane);
+    const int q = decode_block(s_pl + s_pfd[lb], s_wd[lb], s_first[lb], s_sign[lb], lane);
     corrupt |= valid && (q > kQMax || q < -kQMax);
     const float rq = (float)q * two_e;  // float(2q) * e: the same exact product
     float v = rq;
     bool queue = false;
-    if (h.topo) {
-      const int rfirst = *reinterpret_cast<const int*>(a.in + h.off[R4] + 4 * b);
-      const unsigned long long rsign = *reinterpret_cast<const unsigned long long*>(a.in + h.off[R3] + 8 * b);
-      const int dl = decode_block(a.in + h.off[R5] + s_xr + 8ull * s_pfr[lb], s_wr[lb], rfirst, rsign, lane);
+    if (topo) {
+      const int dl = rank_lds ? decode_block(s_rpl + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], lane)
+                              : decode_block(rglob + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], lane);
       corrupt |= valid && (dl < 0 || dl > dmax);
-      const unsigned lw = valid ? *reinterpret_cast<const unsigned*>(a.in + h.off[S6] + 16 * b + 4 * (lane >> 4)) : 0u;
-      const int lab = (int)((lw >> (2 * (lane & 15))) & 3u);
+      const unsigned lw = s_lab[4 * lb + (lane >> 4)];
+      const int lab = valid ? (int)((lw >> (2 * (lane & 15))) & 3u) : CLS_R;
       if (valid && dl > 0 && (lab == CLS_MIN || lab == CLS_MAX)) {
         // flattened extremum: its neighbour maximum (minimum) is its own bin
         // centre, so the stencil value is delta float steps beyond it
@@ -1149,23 +1384,16 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
         }
       }
       queue = valid && dl > 0 && lab == CLS_SAD;
-    }
-    if (valid) a.out[i] = v;
-    if (h.topo) {
       const unsigned long long qm = __ballot(queue);
-      if (lane == 0) bitmap[b] = qm;
+      if (lane == 0) s_bm[lb] = qm;
       if (qm) {
         unsigned base = 0;
         if (lane == 0) base = atomicAdd(&s_qn, (unsigned)__popcll(qm));
         base = (unsigned)__builtin_amdgcn_readlane((int)base, 0);
-        if (queue) {
-          const unsigned pos = base + mbcnt(qm);
-          const long long x = i % nx, t = i / nx, y = t % ny, z = t / ny;
-          s_qi[pos] = (unsigned)i;
-          s_qc[pos] = (uint8_t)(h.ndim == 3 ? (x + 2 * y + 3 * z) % 7 : (x + 2 * y) % 5);
-        }
+        if (queue) qi[base + mbcnt(qm)] = (unsigned)i;
       }
     }
+    if (valid) a.out[i] = v;
   }
   const bool cb = __ballot(corrupt) != 0;
 #pragma unroll
@@ -1179,16 +1407,10 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
     if (cb) atomicOr(&s_corrupt, 1u);
   }
   __syncthreads();
-  // the chunk's queue to its slot range, and its counters
-  const unsigned qn = s_qn;
-  unsigned* qi = reinterpret_cast<unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
-  uint8_t* qc = a.ws + L.col + (size_t)c * kChunk;
-  for (unsigned t = tid; t < qn; t += WAVES * 64) {
-    qi[t] = s_qi[t];
-    qc[t] = s_qc[t];
-  }
+  // the chunk's queued-saddle bitmap and counters
+  if (tid < kB && (uint64_t)c * kB + tid < h.nb) bitmap[(uint64_t)c * kB + tid] = topo ? s_bm[tid] : 0ull;
   if (tid == 0) {
-    reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = qn;
+    reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = s_qn;
     reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = s_moves;
     reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = s_skips;
     dflag[c] = s_corrupt;
@@ -1196,185 +1418,314 @@ __global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Saddle refinement (specialised on the dimension and kernel size, so the
-// neighbourhoods below are compile-time).
+// Saddle refinement (Section IV-B), compiled per (dimension, kernel size) so
+// that every neighbourhood below is a compile-time set of offsets.
+//
+// An evaluation of a queued saddle p reads the cells of its read set: the
+// candidate window (Euclidean distance <= floor(k/2)) and the cells the
+// acceptance tests classify (L1 distance <= 2).  It writes only p.  Queued
+// saddles linked through read-set offsets form clusters; distinct clusters
+// never see each other's updates, so each evolves under the colour-phased
+// schedule exactly as in the whole-field run, and a field-wide round count
+// is the largest of the clusters' (a cluster stops at its first round without
+// a commit; later rounds would not change it).
 
-template <int ND>
-__device__ __forceinline__ int classify_at(const float* fld, int i, Pt c, int pi, float pv, const GeomD& g) {
-  float nb[6];
-  bool av[6];
-  av[0] = c.x > 0;
-  av[1] = c.x < g.nx - 1;
-  av[2] = c.y > 0;
-  av[3] = c.y < g.ny - 1;
-  av[4] = ND == 3 && c.z > 0;
-  av[5] = ND == 3 && c.z < g.nz - 1;
-  const int nbi[6] = {i - 1, i + 1, i - g.nx, i + g.nx, i - g.nxy, i + g.nxy};
-#pragma unroll
-  for (int j = 0; j < 6; ++j) nb[j] = av[j] ? (nbi[j] == pi ? pv : fld[nbi[j]]) : 0.0f;
-  const bool deg[3] = {g.nx < 2, g.ny < 2, ND != 3 || g.nz < 2};
-  const float a = (i == pi) ? pv : fld[i];
-  return classify6(a, nb, av, deg);
-}
-
-// Candidate for a flattened saddle p and the acceptance tests:
-// 0 reject, 1 already a saddle, 2 accept (value in *vout).
 template <int ND, int K>
-__device__ int evaluate(const float* fld, const uint8_t* labels, int p, const Plan& pl, float* vout) {
-  const GeomD& g = pl.g;
-  const Pt c = coords_of(p, g);
-  if (classify_at<ND>(fld, p, c, -1, 0.0f, g) == CLS_SAD) return 1;
-  constexpr int r = K / 2, rz = ND == 3 ? r : 0;
-  double num = 0.0, den = 0.0;
+struct Hood {
+  static constexpr int r = K / 2;
+  static constexpr int R = r > 2 ? r : 2;  // half-width of a box holding the read set
+  static constexpr int RZ = ND == 3 ? R : 0;
+  static constexpr int S = 2 * R + 1;
+  static constexpr int SZ = 2 * RZ + 1;
+  static constexpr int BOX = S * S * SZ;
+  __host__ __device__ static constexpr int iabs(int v) { return v < 0 ? -v : v; }
+  __host__ __device__ static constexpr bool read(int dx, int dy, int dz) {
+    return dx * dx + dy * dy + dz * dz <= r * r || iabs(dx) + iabs(dy) + iabs(dz) <= 2;
+  }
+};
+
+// p's coordinates and the in-range flags of its box offsets.
+template <int ND, int K>
+struct Around {
+  bool xin[Hood<ND, K>::S], yin[Hood<ND, K>::S], zin[Hood<ND, K>::SZ];
+  __device__ __forceinline__ Around(Pt c, const GeomD& g) {
+    using H = Hood<ND, K>;
 #pragma unroll
-  for (int dz = -rz; dz <= rz; ++dz)
+    for (int d = -H::R; d <= H::R; ++d) {
+      xin[d + H::R] = (unsigned)(c.x + d) < (unsigned)g.nx;
+      yin[d + H::R] = (unsigned)(c.y + d) < (unsigned)g.ny;
+    }
+#pragma unroll
+    for (int d = -H::RZ; d <= H::RZ; ++d) zin[d + H::RZ] = (unsigned)(c.z + d) < (unsigned)g.nz;
+  }
+  __device__ __forceinline__ bool in(int dx, int dy, int dz) const {
+    using H = Hood<ND, K>;
+    if (dz < -H::RZ || dz > H::RZ) return false;
+    return zin[dz + H::RZ] && yin[dy + H::R] && xin[dx + H::R];
+  }
+};
+
+// One evaluation of the queued saddle p on the current field: 0 reject,
+// 1 already a saddle, 2 accept (value in *vout).  The cells the
+// classifications read (L1 distance <= 2) are loaded in one batch and kept in
+// registers (addresses outside the grid are replaced by p's own); window
+// cells beyond them are read as the sum reaches them.
+template <int ND, int K>
+__device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels, int p, Pt c,
+                                        const Plan& pl, float* vout) {
+  using H = Hood<ND, K>;
+  constexpr int r = H::r, CZ = ND == 3 ? 2 : 0;  // core: L1 <= 2, box half-width 2
+  const GeomD& g = pl.g;
+  const Around<ND, K> ar(c, g);
+  float v[2 * CZ + 1][5][5];
+#pragma unroll
+  for (int dz = -CZ; dz <= CZ; ++dz)
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) > 2) continue;
+        const int q = ar.in(dx, dy, dz) ? p + dz * g.nxy + dy * g.nx + dx : p;
+        v[dz + CZ][dy + 2][dx + 2] = fld[q];
+      }
+  constexpr int U[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+  int lab[6];
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) {
+    const bool ex = ar.in(U[j][0], U[j][1], U[j][2]);
+    const int q = ex ? p + U[j][2] * g.nxy + U[j][1] * g.nx + U[j][0] : p;
+    lab[j] = (labels[q >> 2] >> (2 * (q & 3))) & 3;
+  }
+  const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
+  // class of the cell at offset o (L1 <= 1) with p's value taken as pv
+  auto cls = [&](int ox, int oy, int oz, float pv) -> int {
+    float nb[6];
+    unsigned avm = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      nb[j] = 0.0f;
+      if (j >= 2 * ND) continue;
+      const int x = ox + U[j][0], y = oy + U[j][1], z = oz + U[j][2];
+      if (ar.in(x, y, z)) avm |= 1u << j;
+      nb[j] = (x == 0 && y == 0 && z == 0) ? pv : v[z + CZ][y + 2][x + 2];
+    }
+    const float a0 = (ox == 0 && oy == 0 && oz == 0) ? pv : v[oz + CZ][oy + 2][ox + 2];
+    return classify_bits(a0, nb, avm, ndeg);
+  };
+  const float p0 = v[CZ][2][2];
+  if (cls(0, 0, 0, p0) == CLS_SAD) return 1;
+  // normalised Gaussian window without p, in (dz, dy, dx) order; cells
+  // outside the grid carry weight 0, which leaves both sums unchanged
+  constexpr int rz = ND == 3 ? r : 0;
+  double num = 0.0, den = 0.0;
+  auto plane = [&](int dz) {
 #pragma unroll
     for (int dy = -r; dy <= r; ++dy)
 #pragma unroll
       for (int dx = -r; dx <= r; ++dx) {
         const int d2 = dz * dz + dy * dy + dx * dx;
         if (d2 == 0 || d2 > r * r) continue;
-        const int zz = c.z + dz, yy = c.y + dy, xx = c.x + dx;
-        if (zz < 0 || zz >= g.nz || yy < 0 || yy >= g.ny || xx < 0 || xx >= g.nx) continue;
-        const double wt = (double)pl.w[d2];
-        num = num + wt * (double)fld[p + dz * g.nxy + dy * g.nx + dx];
+        const bool in = ar.in(dx, dy, dz);
+        const bool core = Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) <= 2;
+        const float x = core ? v[dz + CZ][dy + 2][dx + 2] : fld[in ? p + dz * g.nxy + dy * g.nx + dx : p];
+        const double wt = in ? (double)pl.w[d2] : 0.0;
+        num = num + wt * (double)x;
         den = den + wt;
       }
-  if (den == 0.0) return 0;
-  const float v = (float)(num / den);
-  if (!(fabs((double)v - (double)fld[p]) <= (double)pl.e)) return 0;
-  if (classify_at<ND>(fld, p, c, p, v, g) != CLS_SAD) return 0;
-  const int nbi[6] = {p - 1, p + 1, p - g.nx, p + g.nx, p - g.nxy, p + g.nxy};
-  const Pt nbc[6] = {{c.x - 1, c.y, c.z}, {c.x + 1, c.y, c.z}, {c.x, c.y - 1, c.z},
-                     {c.x, c.y + 1, c.z}, {c.x, c.y, c.z - 1}, {c.x, c.y, c.z + 1}};
-  const bool av[6] = {c.x > 0, c.x < g.nx - 1, c.y > 0, c.y < g.ny - 1,
-                      ND == 3 && c.z > 0, ND == 3 && c.z < g.nz - 1};
+  };
+  if constexpr (ND == 3 && K == 7) {
+    // planes in turn (a runtime loop keeps one plane's loads in registers);
+    // every cell of these planes is read from memory
+#pragma unroll 1
+    for (int dz = -rz; dz <= rz; ++dz) {
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    if (!av[j]) continue;
-    const int q = nbi[j];
-    const int before = classify_at<ND>(fld, q, nbc[j], -1, 0.0f, g);
-    const int after = classify_at<ND>(fld, q, nbc[j], p, v, g);
-    const int lab = (labels[q >> 2] >> (2 * (q & 3))) & 3;
-    if (after != before && !(before == CLS_R && after == lab)) return 0;
+      for (int dy = -r; dy <= r; ++dy)
+#pragma unroll
+        for (int dx = -r; dx <= r; ++dx) {
+          const int d2 = dz * dz + dy * dy + dx * dx;
+          if (d2 == 0 || d2 > r * r) continue;
+          const bool in = ar.in(dx, dy, dz);
+          const float x = fld[in ? p + dz * g.nxy + dy * g.nx + dx : p];
+          const double wt = in ? (double)pl.w[d2] : 0.0;
+          num = num + wt * (double)x;
+          den = den + wt;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int dz = -rz; dz <= rz; ++dz) plane(dz);
   }
-  *vout = v;
+  if (den == 0.0) return 0;
+  const float cand = (float)(num / den);
+  if (!(fabs((double)cand - (double)p0) <= (double)pl.e)) return 0;
+  if (cls(0, 0, 0, cand) != CLS_SAD) return 0;
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) {
+    if (!ar.in(U[j][0], U[j][1], U[j][2])) continue;
+    const int before = cls(U[j][0], U[j][1], U[j][2], p0);
+    const int after = cls(U[j][0], U[j][1], U[j][2], cand);
+    if (after != before && !(before == CLS_R && after == lab[j])) return 0;
+  }
+  *vout = cand;
   return 2;
 }
 
-__device__ __forceinline__ int colour_of(int i, const GeomD& g, int ndim) {
-  const Pt c = coords_of(i, g);
+__device__ __forceinline__ int colour_of(Pt c, int ndim) {
   return ndim == 3 ? (int)(((unsigned)c.x + 2u * (unsigned)c.y + 3u * (unsigned)c.z) % 7u)
                    : (int)(((unsigned)c.x + 2u * (unsigned)c.y) % 5u);
 }
 
-// Offsets through which two queued saddles can influence each other's
-// evaluation: the candidate window (Euclidean radius floor(k/2)) and the
-// cells the acceptance tests classify (L1 distance <= 2).
-__host__ __device__ constexpr bool in_reach(int dx, int dy, int dz, int r) {
-  return (dx * dx + dy * dy + dz * dz) > 0 &&
-         ((dx * dx + dy * dy + dz * dz) <= r * r ||
-          (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz) <= 2);
-}
-
-// Queued saddles within reach of cur, appended to mem[m..] if new; returns
-// false when the list would exceed kClusterMax.
+// Queued saddles among p's read set (p excluded): any, and any with a
+// smaller flat index.
 template <int ND, int K>
-__device__ __forceinline__ bool gather(const unsigned long long* bm, int cur, const GeomD& g, unsigned* mem,
-                                       int& m) {
-  constexpr int r = K / 2, R = r > 2 ? r : 2, RZ = ND == 3 ? R : 0;
-  const Pt c = coords_of(cur, g);
+__device__ __forceinline__ void reach(const unsigned long long* bm, int p, Pt c, const GeomD& g, bool& any,
+                                      bool& smaller) {
+  using H = Hood<ND, K>;
+  const Around<ND, K> ar(c, g);
+  any = smaller = false;
+  auto plane = [&](int dz) {
 #pragma unroll
-  for (int dz = -RZ; dz <= RZ; ++dz)
+    for (int dy = -H::R; dy <= H::R; ++dy)
 #pragma unroll
-    for (int dy = -R; dy <= R; ++dy)
-#pragma unroll
-      for (int dx = -R; dx <= R; ++dx) {
-        if (!in_reach(dx, dy, dz, r)) continue;
-        const int xx = c.x + dx, yy = c.y + dy, zz = c.z + dz;
-        const bool in = xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz;
-        const int q = cur + dz * g.nxy + dy * g.nx + dx;
-        const unsigned long long word = in ? bm[q >> 6] : 0ull;
-        if (!((word >> (q & 63)) & 1ull)) continue;
-        bool seen = false;
-        for (int j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
-        if (seen) continue;
-        if (m == kClusterMax) return false;
-        mem[m++] = (unsigned)q;
+      for (int dx = -H::R; dx <= H::R; ++dx) {
+        if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
+        const bool in = ar.in(dx, dy, dz);
+        const int q = in ? p + dz * g.nxy + dy * g.nx + dx : p;
+        const bool hit = in && ((bm[q >> 6] >> (q & 63)) & 1ull);
+        any |= hit;
+        if (dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)))) smaller |= hit;
       }
-  return true;
+  };
+  if constexpr (ND == 3 && K == 7) {
+#pragma unroll 1
+    for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);  // a plane's loads at a time
+  } else {
+#pragma unroll
+    for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+  }
 }
 
+constexpr int kWaveCluster = 64;  // cluster members one wave replays (one per lane)
+constexpr int kCandMax = 1024;    // cluster owners per chunk held in LDS per pass
+
 template <int ND, int K>
-__device__ void refine_chunk(const RefArgs& a, const Plan& pl, unsigned* mem, float* val, uint8_t* st,
-                             unsigned& my_commits, unsigned& my_rounds) {
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x;
+__device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, unsigned* s_cand, unsigned& s_nc,
+                             unsigned (*s_mem)[kWaveCluster], unsigned& commits, unsigned& rounds) {
+  using H = Hood<ND, K>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint64_t nb = ((uint64_t)pl.g.n + kB - 1) / kB;
   const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
   const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
   const unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
-  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
+  const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
   const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
-  unsigned* big = reinterpret_cast<unsigned*>(a.ws + L.big);
   const uint8_t* labels = a.in + pl.s6_off;
-  for (unsigned t = tid; t < cnt; t += kRefineThreads) {
-    const unsigned slot = (unsigned)c * kChunk + t;
-    const int p = (int)idx[slot];
-    // the connected set of queued saddles around p (bounded)
-    mem[0] = (unsigned)p;
-    int m = 1, head = 0;
-    bool fits = true;
-    while (head < m && fits) fits = gather<ND, K>(bm, (int)mem[head++], pl.g, mem, m);
-    if (!fits) {
-      // left to the tail kernel (every member's search overflows the same way)
-      const unsigned pos = atomicAdd(&ctrl_of(a.ws)->big_count, 1u);
-      if (pos < (unsigned)pl.nch * kChunk) big[pos] = slot;
-      continue;
-    }
-    unsigned owner = mem[0];
-    for (int j = 1; j < m; ++j) owner = min(owner, mem[j]);
-    if (owner != (unsigned)p) continue;  // another thread replays this cluster
-    // replay the colour-phased rounds on the cluster (Jacobi within a phase)
-    for (int j = 0; j < m; ++j) st[j] = (uint8_t)(colour_of((int)mem[j], pl.g, ND) << 2);
-    int round = 1;
-    for (; round <= pl.max_rounds; ++round) {
-      unsigned commits = 0;
-      for (int cc = 0; cc < pl.ncol; ++cc) {
-        bool any = false;
-        for (int j = 0; j < m; ++j) {
-          if ((st[j] & 3) == 1 || (st[j] >> 2) != cc) continue;
-          float v;
-          const int res = evaluate<ND, K>(a.out, labels, (int)mem[j], pl, &v);
-          if (res == 1) {
-            st[j] = (uint8_t)((st[j] & ~3) | 1);
-          } else if (res == 2) {
-            st[j] = (uint8_t)((st[j] & ~3) | 2);
-            val[j] = v;
-            any = true;
-          }
+  const GeomD& g = pl.g;
+  const int cap = pl.max_rounds;
+
+  for (unsigned base = 0; base < cnt; base += kCandMax) {
+    // phase A, one lane per queued saddle: isolated saddles are settled by
+    // one evaluation; a cluster's smallest member becomes its owner
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    const unsigned lim = min(cnt, base + kCandMax);
+    for (unsigned t = base + tid; t < lim; t += 256) {
+      const int p = (int)idx[t];
+      const Pt pc = coords_of(p, g);
+      bool any, smaller;
+      reach<ND, K>(bm, p, pc, g, any, smaller);
+      if (!any) {
+        float v;
+        const int res = evaluate<ND, K>(a.out, labels, p, pc, pl, &v);
+        if (res == 2) {
+          a.out[p] = v;
+          ++commits;
         }
-        if (!any) continue;
-        for (int j = 0; j < m; ++j)
-          if ((st[j] & 3) == 2) {
-            a.out[mem[j]] = val[j];
-            st[j] = (uint8_t)((st[j] & ~3) | 1);
-            ++commits;
-          }
+        rounds = max(rounds, (unsigned)min(res == 2 ? 2 : 1, cap));
+      } else if (!smaller) {
+        s_cand[atomicAdd(&s_nc, 1u)] = (unsigned)p;
       }
-      my_commits += commits;
-      if (commits == 0) break;
     }
-    my_rounds = max(my_rounds, (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds));
+    __syncthreads();
+    // phase B, one wave per owner: gather the cluster (in lane order), then
+    // replay the schedule with one member per lane
+    const unsigned nc = s_nc;
+    unsigned* mem = s_mem[wv];
+    for (unsigned k = wv; k < nc; k += 4) {
+      const unsigned p0 = s_cand[k];
+      if (lane == 0) mem[0] = p0;
+      int m = 1;
+      bool owner = true, over = false;
+      for (int head = 0; head < m && owner && !over; ++head) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cur = (int)mem[head];
+        const Pt cc = coords_of(cur, g);
+        const Around<ND, K> ar(cc, g);
+        // every lane runs every pass (the counts below must stay uniform)
+        for (int b0 = 0; b0 < H::BOX; b0 += 64) {
+          const int bx = b0 + lane;
+          const int dx = bx % H::S - H::R, dy = (bx / H::S) % H::S - H::R, dz = bx / (H::S * H::S) - H::RZ;
+          bool hit = false;
+          int q = cur;
+          if (bx < H::BOX && H::read(dx, dy, dz) && !(dx == 0 && dy == 0 && dz == 0) && ar.in(dx, dy, dz)) {
+            q = cur + dz * g.nxy + dy * g.nx + dx;
+            hit = (bm[q >> 6] >> (q & 63)) & 1ull;
+          }
+          for (int j = 0; j < m && hit; ++j) hit = mem[j] != (unsigned)q;  // new members only
+          const unsigned long long nm = __ballot(hit);
+          if ((unsigned)m + (unsigned)__popcll(nm) > (unsigned)kWaveCluster) {
+            over = true;
+            break;
+          }
+          if (__ballot(hit && (unsigned)q < p0)) owner = false;  // a smaller member owns it
+          if (hit) mem[m + mbcnt(nm)] = (unsigned)q;
+          m += __popcll(nm);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+      if (over) {
+        if (lane == 0) atomicOr(&ctrl_of(a.ws)->big, 1u);  // left to the whole-field replay
+        continue;
+      }
+      if (!owner) continue;
+      const bool act = lane < m;
+      const int my = act ? (int)mem[lane] : (int)p0;
+      const Pt myc = coords_of(my, g);
+      const int col = colour_of(myc, ND);
+      bool settled = !act;
+      int round = 1;
+      for (; round <= cap; ++round) {
+        unsigned long long cm = 0;
+        for (int ph = 0; ph < pl.ncol; ++ph) {
+          // Jacobi within the phase: all evaluations read, then commit
+          int res = 0;
+          float v = 0.0f;
+          if (!settled && col == ph) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
+          if (res != 0) settled = true;
+          if (res == 2) a.out[my] = v;
+          const unsigned long long pm = __ballot(res == 2);
+          cm |= pm;
+          if (pm) __threadfence_block();
+        }
+        commits += lane == 0 ? (unsigned)__popcll(cm) : 0u;
+        if (!cm) break;
+      }
+      rounds = max(rounds, (unsigned)min(round, cap));
+    }
+    __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_mem[kRefineThreads][kClusterMax];
-  __shared__ float s_val[kRefineThreads][kClusterMax];
-  __shared__ uint8_t s_st[kRefineThreads][kClusterMax];
-  __shared__ unsigned s_commits, s_rounds, s_ok;
+  __shared__ unsigned s_cand[kCandMax];
+  __shared__ unsigned s_mem[4][kWaveCluster];
+  __shared__ unsigned s_nc, s_commits, s_rounds, s_ok;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -1385,22 +1736,27 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
   }
   __syncthreads();
   const Plan& pl = s_p;
-  const int c = blockIdx.x;
-  if (!s_ok || c >= pl.nch) return;
-  unsigned my_commits = 0, my_rounds = 0;
-  unsigned* mem = s_mem[tid];
-  float* val = s_val[tid];
-  uint8_t* st = s_st[tid];
+  if (!s_ok || (int)blockIdx.x >= xcd_grid(pl.nch)) return;
+  const int c = xcd_chunk(blockIdx.x, pl.nch);
+  if (c >= pl.nch) return;
+  unsigned commits = 0, rounds = 0;
   switch (pl.ndim * 8 + pl.k) {
-    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, mem, val, st, my_commits, my_rounds); break;
-    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, mem, val, st, my_commits, my_rounds); break;
-    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, mem, val, st, my_commits, my_rounds); break;
-    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, mem, val, st, my_commits, my_rounds); break;
-    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, mem, val, st, my_commits, my_rounds); break;
-    default: refine_chunk<3, 7>(a, pl, mem, val, st, my_commits, my_rounds); break;
+    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    default: refine_chunk<3, 7>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
   }
-  if (my_commits) atomicAdd(&s_commits, my_commits);
-  if (my_rounds) atomicMax(&s_rounds, my_rounds);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    commits += (unsigned)__shfl_xor((int)commits, o);
+    rounds = max(rounds, (unsigned)__shfl_xor((int)rounds, o));
+  }
+  if ((tid & 63) == 0) {
+    if (commits) atomicAdd(&s_commits, commits);
+    if (rounds) atomicMax(&s_rounds, rounds);
+  }
   __syncthreads();
   if (tid == 0 && (s_commits || s_rounds)) {
     Spread* sp = spread_of(a.ws) + (c % kSpreadLines);
@@ -1409,47 +1765,57 @@ __global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefArgs a) {
   }
 }
 
-// Clusters too large for one thread: the colour-phased rounds by one
-// workgroup with workgroup barriers (rare).  Then status and counters.
+// Whole-field replay of the schedule over every queued saddle, by one
+// workgroup with workgroup barriers.  Runs only when some cluster was too
+// large for a wave; clusters already settled by the refine kernel neither
+// commit nor change here (their inputs are unchanged), so only the large
+// ones progress.  Returns the rounds run; commits go to stats[1].
 template <int ND, int K>
-__device__ unsigned tail_rounds(const RefArgs& a, const Plan& pl, const DecLayout& L, unsigned nbig) {
+__device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout& L) {
   __shared__ unsigned s_commits;
-  const unsigned* bigl = reinterpret_cast<const unsigned*>(a.ws + L.big);
+  const unsigned* cnt = reinterpret_cast<const unsigned*>(a.ws + L.cnt);
   const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx);
-  const uint8_t* col = a.ws + L.col;
   uint8_t* state = a.ws + L.state;
   float* pend = reinterpret_cast<float*>(a.ws + L.pend);
   const uint8_t* labels = a.in + pl.s6_off;
   const unsigned tid = threadIdx.x, nthr = blockDim.x;
-  for (unsigned t = tid; t < nbig; t += nthr) state[bigl[t]] = 0;
+  for (int c = 0; c < pl.nch; ++c)
+    for (unsigned t = tid; t < min(cnt[c], (unsigned)kChunk); t += nthr) state[(size_t)c * kChunk + t] = 0;
   __syncthreads();
   int round = 1;
-  unsigned total = 0;
+  unsigned long long total = 0;
   for (; round <= pl.max_rounds; ++round) {
     if (tid == 0) s_commits = 0;
     __syncthreads();
-    for (int cc = 0; cc < pl.ncol; ++cc) {
-      // Jacobi within the phase: evaluate every candidate, then commit
-      for (unsigned t = tid; t < nbig; t += nthr) {
-        const unsigned s = bigl[t];
-        if (state[s] || col[s] != cc) continue;
-        float v;
-        const int res = evaluate<ND, K>(a.out, labels, (int)idx[s], pl, &v);
-        if (res == 1) {
-          state[s] = 1;
-        } else if (res == 2) {
-          pend[s] = v;
-          state[s] = 2;
-          atomicAdd(&s_commits, 1u);
+    for (int ph = 0; ph < pl.ncol; ++ph) {
+      for (int c = 0; c < pl.nch; ++c) {
+        const unsigned n = min(cnt[c], (unsigned)kChunk);
+        for (unsigned t = tid; t < n; t += nthr) {
+          const size_t sl = (size_t)c * kChunk + t;
+          const int p = (int)idx[sl];
+          const Pt pc = coords_of(p, pl.g);
+          if (state[sl] || colour_of(pc, ND) != ph) continue;
+          float v;
+          const int res = evaluate<ND, K>(a.out, labels, p, pc, pl, &v);
+          if (res == 1) {
+            state[sl] = 1;
+          } else if (res == 2) {
+            pend[sl] = v;
+            state[sl] = 2;
+            atomicAdd(&s_commits, 1u);
+          }
         }
       }
       __threadfence_block();
       __syncthreads();
-      for (unsigned t = tid; t < nbig; t += nthr) {
-        const unsigned s = bigl[t];
-        if (state[s] == 2) {
-          a.out[idx[s]] = pend[s];
-          state[s] = 1;
+      for (int c = 0; c < pl.nch; ++c) {
+        const unsigned n = min(cnt[c], (unsigned)kChunk);
+        for (unsigned t = tid; t < n; t += nthr) {
+          const size_t sl = (size_t)c * kChunk + t;
+          if (state[sl] == 2) {
+            a.out[idx[sl]] = pend[sl];
+            state[sl] = 1;
+          }
         }
       }
       __threadfence_block();
@@ -1461,23 +1827,25 @@ __device__ unsigned tail_rounds(const RefArgs& a, const Plan& pl, const DecLayou
     if (commits == 0) break;
   }
   if (tid == 0) ctrl_of(a.ws)->stats[1] = total;
-  return (unsigned)(round <= pl.max_rounds ? round : pl.max_rounds);
+  return (unsigned)min(round, pl.max_rounds);
 }
 
+// Status and counters of the decompression (one workgroup), after the
+// whole-field replay when a cluster needed it.
 __global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_big, s_ok, s_hf;
-  __shared__ unsigned long long s_sum[3];
-  __shared__ unsigned s_fl;
+  __shared__ unsigned s_big, s_ok, s_hf, s_fl, s_rounds;
+  __shared__ unsigned long long s_sum[4];
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_p = ct->plan;
     s_hf = ct->hflags;
     s_ok = s_hf == 0 && s_p.valid;
-    s_big = ct->big_count;
-    s_sum[0] = s_sum[1] = s_sum[2] = 0;
+    s_big = ct->big;
+    s_sum[0] = s_sum[1] = s_sum[2] = s_sum[3] = 0;
     s_fl = 0;
+    s_rounds = 0;
     ct->stats[1] = 0;
   }
   __syncthreads();
@@ -1485,22 +1853,20 @@ __global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
   const bool ok = s_ok != 0;
   const uint64_t nb = ok ? ((uint64_t)pl.g.n + kB - 1) / kB : 0;
   const DecLayout L = dec_layout(nb, ok ? (uint64_t)pl.nch : 0);
-  const unsigned cap = ok ? (unsigned)pl.nch * kChunk : 0;
-  const unsigned nbig = ok && pl.topo ? (s_big < cap ? s_big : cap) : 0;
   unsigned trounds = 0;
-  if (nbig > 0) {
+  if (ok && pl.topo && s_big) {
     switch (pl.ndim * 8 + pl.k) {
-      case 2 * 8 + 3: trounds = tail_rounds<2, 3>(a, pl, L, nbig); break;
-      case 2 * 8 + 5: trounds = tail_rounds<2, 5>(a, pl, L, nbig); break;
-      case 2 * 8 + 7: trounds = tail_rounds<2, 7>(a, pl, L, nbig); break;
-      case 3 * 8 + 3: trounds = tail_rounds<3, 3>(a, pl, L, nbig); break;
-      case 3 * 8 + 5: trounds = tail_rounds<3, 5>(a, pl, L, nbig); break;
-      default: trounds = tail_rounds<3, 7>(a, pl, L, nbig); break;
+      case 2 * 8 + 3: trounds = replay_all<2, 3>(a, pl, L); break;
+      case 2 * 8 + 5: trounds = replay_all<2, 5>(a, pl, L); break;
+      case 2 * 8 + 7: trounds = replay_all<2, 7>(a, pl, L); break;
+      case 3 * 8 + 3: trounds = replay_all<3, 3>(a, pl, L); break;
+      case 3 * 8 + 5: trounds = replay_all<3, 5>(a, pl, L); break;
+      default: trounds = replay_all<3, 7>(a, pl, L); break;
     }
   }
   __syncthreads();
-  unsigned long long q = 0, mv = 0, sk = 0;
-  unsigned fl = 0;
+  unsigned long long q = 0, mv = 0, sk = 0, cm = 0;
+  unsigned fl = 0, rd = 0;
   if (ok) {
     const unsigned* cnt = reinterpret_cast<const unsigned*>(a.ws + L.cnt);
     const unsigned* mo = reinterpret_cast<const unsigned*>(a.ws + L.moves);
@@ -1513,19 +1879,32 @@ __global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
       fl |= df[k];
     }
   }
-  atomicAdd(&s_sum[0], q);
-  atomicAdd(&s_sum[1], mv);
-  atomicAdd(&s_sum[2], sk);
-  if (fl) atomicOr(&s_fl, fl);
+  if (tid < kSpreadLines) {
+    const Spread* sp = spread_of(a.ws) + tid;
+    cm = sp->commits;
+    rd = sp->rounds;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    q += __shfl_xor(q, o);
+    mv += __shfl_xor(mv, o);
+    sk += __shfl_xor(sk, o);
+    cm += __shfl_xor(cm, o);
+    fl |= (unsigned)__shfl_xor((int)fl, o);
+    rd = max(rd, (unsigned)__shfl_xor((int)rd, o));
+  }
+  if ((tid & 63) == 0) {
+    atomicAdd(&s_sum[0], q);
+    atomicAdd(&s_sum[1], mv);
+    atomicAdd(&s_sum[2], sk);
+    atomicAdd(&s_sum[3], cm);
+    if (fl) atomicOr(&s_fl, fl);
+    if (rd) atomicMax(&s_rounds, rd);
+  }
   __syncthreads();
   if (tid == 0) {
-    const Spread* sp = spread_of(a.ws);
-    unsigned long long commits = ct->stats[1];
-    unsigned rounds = trounds;
-    for (int k = 0; k < kSpreadLines; ++k) {
-      commits += sp[k].commits;
-      rounds = max(rounds, sp[k].rounds);
-    }
+    const unsigned long long commits = ct->stats[1] + s_sum[3];
+    unsigned rounds = max(trounds, s_rounds);
     if (ok && pl.topo && rounds == 0) rounds = 1;  // a round that found nothing to do
     ct->stats[0] = ok && pl.topo ? rounds : 0;
     ct->stats[1] = commits;
@@ -1604,8 +1983,6 @@ void ev_end(int k, hipStream_t s) {
   g_ev_used[k] = true;
 }
 
-constexpr int kEncWaves = 4;
-constexpr int kDecWaves = 4;
 
 }  // namespace
 
@@ -1674,7 +2051,7 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
 
-  int nrange = (int)((hg.g.n / 4 + 4095) / 4096);
+  int nrange = (int)((hg.g.n / 4 + 256 * kRangeVec - 1) / (256 * kRangeVec));
   if (nrange > kRangeWG) nrange = kRangeWG;
   if (nrange < 1) nrange = 1;
   const float e_abs = host_round_down(eb);
@@ -1721,6 +2098,9 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   fa.rbf_policy = p.rbf_policy;
   fa.max_rounds = p.max_rounds;
   fa.eb = eb;
+  fa.e_abs = e_abs;
+  fa.nrange = nrange;
+  fa.fused = ea.nch <= kFuseMax ? 1 : 0;
   memcpy(fa.off, ea.off, sizeof(ea.off));
   memcpy(fa.len, ea.len, sizeof(ea.len));
   const double sig[3] = {0.5, 0.75, 1.0};
@@ -1734,11 +2114,14 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     ev_end(0, s);
   }
   ev_begin(1, s);
-  hipLaunchKernelGGL(encode_kernel<kEncWaves>, dim3(ea.nch), dim3(kEncWaves * 64), 0, s, ea);
+  if (hg.g.ndim == 3)
+    hipLaunchKernelGGL(encode_kernel<3>, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, ea);
+  else
+    hipLaunchKernelGGL(encode_kernel<2>, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, ea);
   ev_end(1, s);
   ev_begin(2, s);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sa);
-  hipLaunchKernelGGL(finalize_kernel, dim3(ea.nch), dim3(256), 0, s, fa);
+  if (!fa.fused) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sa);
+  hipLaunchKernelGGL(finalize_kernel, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, fa);
   ev_end(2, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
@@ -1762,7 +2145,7 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   da.ws_bytes = ws_bytes;
   for (int k = 3; k < 5; ++k) g_ev_used[k] = false;
   ev_begin(3, s);
-  hipLaunchKernelGGL(decode_kernel<kDecWaves>, dim3((unsigned)nch), dim3(kDecWaves * 64), 0, s, da);
+  hipLaunchKernelGGL(decode_kernel, dim3(xcd_grid((int)nch)), dim3(256), 0, s, da);
   ev_end(3, s);
   RefArgs ra;
   ra.in = d_in;
@@ -1770,7 +2153,7 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   ra.ws = (uint8_t*)d_ws;
   ra.status = d_status;
   ev_begin(4, s);
-  hipLaunchKernelGGL(refine_kernel, dim3((unsigned)nch), dim3(kRefineThreads), 0, s, ra);
+  hipLaunchKernelGGL(refine_kernel, dim3(xcd_grid((int)nch)), dim3(256), 0, s, ra);
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, ra);
   ev_end(4, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;

@@ -18,6 +18,8 @@ __all__ = [
     "sinusoids_2d",
     "grf_3d",
     "noise",
+    "checker_2d",
+    "checker_3d",
     "cfg0",
     "cfg1",
     "cfg2",
@@ -108,6 +110,26 @@ def noise(shape, seed: int = 0, dist: str = "normal") -> np.ndarray:
 
 
 # Named workloads --------------------------------------------------------------
+
+def checker_2d(ny: int, nx: int, seed: int = 0, a: float = 1.0, b: float = 0.7,
+               noise_sd: float = 0.5, ramp: float = 0.05) -> np.ndarray:
+    """a(-1)^x - b(-1)^y on vertical bands (where sin(x/5) > -0.3), plus a
+    ramp 0.05 x and N(0, noise_sd^2) noise: dense alternating extrema and
+    saddles whose neighbourhoods overlap."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    base = a * (-1.0) ** x - b * (-1.0) ** y
+    f = base * (np.sin(x / 5.0) > -0.3) + noise_sd * rng.standard_normal((ny, nx)) + ramp * x
+    return f.astype(np.float32)
+
+
+def checker_3d(n0: int, n1: int, n2: int, seed: int = 0, noise_sd: float = 0.2) -> np.ndarray:
+    """(-1)^x - 0.6(-1)^y + 0.3(-1)^z plus N(0, noise_sd^2) noise."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.mgrid[0:n0, 0:n1, 0:n2].astype(np.float64)
+    f = (-1.0) ** x - 0.6 * (-1.0) ** y + 0.3 * (-1.0) ** z + noise_sd * rng.standard_normal((n0, n1, n2))
+    return f.astype(np.float32)
+
 
 def cfg0() -> np.ndarray:
     """512 x 512, 40 Gaussian bumps + N(0, 1e-3^2) noise, seed 0."""

@@ -124,6 +124,20 @@ def test_parity_kernel_sizes(tsz, ora):
     assert len(ks) >= 3
 
 
+def test_parity_large_clusters(tsz, ora):
+    # queued saddles linked into clusters of hundreds of members (beyond one
+    # wave), with commits: the whole-field replay path
+    res = check(tsz, ora, "checker2d", datagen.checker_2d(40, 48, seed=0), 2.0, "abs")
+    assert res[2]["commits"] > 0
+    res = check(tsz, ora, "checker3d", datagen.checker_3d(10, 12, 14, seed=11), 1.0, "abs")
+    assert res[2]["commits"] > 0
+    # the same patterns tiled next to smooth regions: large and small
+    # clusters in one field
+    f = datagen.gaussian_bumps_2d(120, 150, 12, seed=9)
+    f[30:70, 40:88] = datagen.checker_2d(40, 48, seed=1) * 0.05 + f[30:70, 40:88]
+    check(tsz, ora, "checker_in_bumps", f, 2e-2, "rel")
+
+
 def test_parity_plain_szp(tsz, ora):
     check(tsz, ora, "plain", datagen.gaussian_bumps_2d(90, 110, 5, seed=9), 1e-3, "rel", topo=False)
     check(tsz, ora, "plain3d", datagen.grf_3d(10, 12, 14, seed=9), 1e-3, "rel", topo=False)
