@@ -1442,6 +1442,10 @@ struct Hood {
   __host__ __device__ static constexpr bool read(int dx, int dy, int dz) {
     return dx * dx + dy * dy + dz * dz <= r * r || iabs(dx) + iabs(dy) + iabs(dz) <= 2;
   }
+  // any offset: inside the box and in the read set
+  __host__ __device__ static constexpr bool reads(int dx, int dy, int dz) {
+    return iabs(dx) <= R && iabs(dy) <= R && iabs(dz) <= RZ && read(dx, dy, dz);
+  }
 };
 
 // p's coordinates and the in-range flags of its box offsets.
@@ -1605,15 +1609,75 @@ __device__ __forceinline__ void reach(const unsigned long long* bm, int p, Pt c,
   }
 }
 
-constexpr int kWaveCluster = 64;  // cluster members one wave replays (one per lane)
-constexpr int kCandMax = 1024;    // cluster owners per chunk held in LDS per pass
+constexpr int kClusterMax = 64;   // members of a cluster replayed in a workgroup
+#ifndef TSZ_REFINE_WAVES
+#define TSZ_REFINE_WAVES 2
+#endif
+constexpr int kRefThreads = 64 * TSZ_REFINE_WAVES;  // refine workgroup
+constexpr int kCandMax = 1024;                       // cluster owners per chunk per pass
+constexpr int kBatch = 32;                           // owners gathered at once
+
+// LDS of the refine kernel.
+struct RefShared {
+  unsigned cand[kCandMax];          // owners found in phase A
+  unsigned memb[kBatch][kClusterMax];  // their clusters
+  unsigned msize[kBatch];           // member count; 0 = not an owner or too large
+  unsigned off[kBatch + 1];         // first lane of each cluster in the pack
+  unsigned cflag[kBatch];           // bit0 still running, bit1 committed this round
+  unsigned crounds[kBatch];
+  unsigned cpts[kRefThreads];       // points committed in the current phase
+  unsigned nc, ncp, any;
+};
+
+// Gathers the cluster of owner candidate p0 (lane-serial): every queued
+// saddle reachable through read-set offsets.  Returns the member count, or
+// 0 if a smaller member exists (it owns the cluster) or there are more than
+// kClusterMax members (*over set).
+template <int ND, int K>
+__device__ unsigned gather(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
+                           bool* over) {
+  using H = Hood<ND, K>;
+  mem[0] = p0;
+  unsigned m = 1;
+  bool owner = true;
+  *over = false;
+  for (unsigned head = 0; head < m && owner && !*over; ++head) {
+    const int cur = (int)mem[head];
+    const Pt cc = coords_of(cur, g);
+    const Around<ND, K> ar(cc, g);
+    auto plane = [&](int dz) {
+#pragma unroll
+      for (int dy = -H::R; dy <= H::R; ++dy)
+#pragma unroll
+        for (int dx = -H::R; dx <= H::R; ++dx) {
+          if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
+          const bool in = ar.in(dx, dy, dz);
+          const int q = in ? cur + dz * g.nxy + dy * g.nx + dx : cur;
+          if (!(in && ((bm[q >> 6] >> (q & 63)) & 1ull))) continue;
+          bool seen = false;
+          for (unsigned j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
+          if (seen) continue;
+          if ((unsigned)q < p0) owner = false;
+          if (m == (unsigned)kClusterMax) *over = true;
+          else mem[m++] = (unsigned)q;
+        }
+    };
+    if constexpr (ND == 3 && K == 7) {
+#pragma unroll 1
+      for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+    } else {
+#pragma unroll
+      for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+    }
+  }
+  return owner && !*over ? m : 0u;
+}
 
 template <int ND, int K>
-__device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, unsigned* s_cand, unsigned& s_nc,
-                             unsigned (*s_mem)[kWaveCluster], unsigned& commits, unsigned& rounds) {
+__device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared& sh, unsigned& commits,
+                             unsigned& rounds) {
   using H = Hood<ND, K>;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tid = threadIdx.x;
   const uint64_t nb = ((uint64_t)pl.g.n + kB - 1) / kB;
   const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
   const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
@@ -1626,106 +1690,128 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, unsigned* 
 
   for (unsigned base = 0; base < cnt; base += kCandMax) {
     // phase A, one lane per queued saddle: isolated saddles are settled by
-    // one evaluation; a cluster's smallest member becomes its owner
-    if (tid == 0) s_nc = 0;
+    // one evaluation; a saddle with no smaller queued saddle in reach owns
+    // its cluster (if it is the cluster's smallest member)
+    if (tid == 0) sh.nc = 0;
     __syncthreads();
     const unsigned lim = min(cnt, base + kCandMax);
-    for (unsigned t = base + tid; t < lim; t += 256) {
+    for (unsigned t = base + tid; t < lim; t += kRefThreads) {
       const int p = (int)idx[t];
       const Pt pc = coords_of(p, g);
+      // the reach test and the evaluation read disjoint data: both go out
+      // at once, and the evaluation counts only for an isolated saddle
       bool any, smaller;
       reach<ND, K>(bm, p, pc, g, any, smaller);
+      float v = 0.0f;
+      const int res = evaluate<ND, K>(a.out, labels, p, pc, pl, &v);
       if (!any) {
-        float v;
-        const int res = evaluate<ND, K>(a.out, labels, p, pc, pl, &v);
         if (res == 2) {
           a.out[p] = v;
           ++commits;
         }
         rounds = max(rounds, (unsigned)min(res == 2 ? 2 : 1, cap));
       } else if (!smaller) {
-        s_cand[atomicAdd(&s_nc, 1u)] = (unsigned)p;
+        sh.cand[atomicAdd(&sh.nc, 1u)] = (unsigned)p;
       }
     }
     __syncthreads();
-    // phase B, one wave per owner: gather the cluster (in lane order), then
-    // replay the schedule with one member per lane
-    const unsigned nc = s_nc;
-    unsigned* mem = s_mem[wv];
-    for (unsigned k = wv; k < nc; k += 4) {
-      const unsigned p0 = s_cand[k];
-      if (lane == 0) mem[0] = p0;
-      int m = 1;
-      bool owner = true, over = false;
-      for (int head = 0; head < m && owner && !over; ++head) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int cur = (int)mem[head];
-        const Pt cc = coords_of(cur, g);
-        const Around<ND, K> ar(cc, g);
-        // every lane runs every pass (the counts below must stay uniform)
-        for (int b0 = 0; b0 < H::BOX; b0 += 64) {
-          const int bx = b0 + lane;
-          const int dx = bx % H::S - H::R, dy = (bx / H::S) % H::S - H::R, dz = bx / (H::S * H::S) - H::RZ;
-          bool hit = false;
-          int q = cur;
-          if (bx < H::BOX && H::read(dx, dy, dz) && !(dx == 0 && dy == 0 && dz == 0) && ar.in(dx, dy, dz)) {
-            q = cur + dz * g.nxy + dy * g.nx + dx;
-            hit = (bm[q >> 6] >> (q & 63)) & 1ull;
-          }
-          for (int j = 0; j < m && hit; ++j) hit = mem[j] != (unsigned)q;  // new members only
-          const unsigned long long nm = __ballot(hit);
-          if ((unsigned)m + (unsigned)__popcll(nm) > (unsigned)kWaveCluster) {
-            over = true;
-            break;
-          }
-          if (__ballot(hit && (unsigned)q < p0)) owner = false;  // a smaller member owns it
-          if (hit) mem[m + mbcnt(nm)] = (unsigned)q;
-          m += __popcll(nm);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const unsigned nc = sh.nc;
+
+    // phase B, kBatch owners at a time: each gathers its cluster in its own
+    // lane; the clusters are then packed one member per lane and replayed
+    // together under the colour-phased schedule
+    for (unsigned b0 = 0; b0 < nc; b0 += kBatch) {
+      const unsigned nbat = min(nc - b0, (unsigned)kBatch);
+      if ((unsigned)tid < nbat) {
+        bool over;
+        sh.msize[tid] = gather<ND, K>(bm, sh.cand[b0 + tid], g, sh.memb[tid], &over);
+        if (over) atomicOr(&ctrl_of(a.ws)->big, 1u);  // left to the whole-field replay
+      }
+      __syncthreads();
+      for (unsigned k0 = 0; k0 < nbat;) {
+        // pack clusters k0.. while they fit the workgroup
+        unsigned k1 = k0, tot = 0;
+        while (k1 < nbat && tot + sh.msize[k1] <= (unsigned)kRefThreads) tot += sh.msize[k1++];
+        if ((unsigned)tid <= k1 - k0) {
+          unsigned o = 0;
+          for (unsigned j = k0; j < k0 + tid; ++j) o += sh.msize[j];
+          sh.off[tid] = o;
         }
-      }
-      if (over) {
-        if (lane == 0) atomicOr(&ctrl_of(a.ws)->big, 1u);  // left to the whole-field replay
-        continue;
-      }
-      if (!owner) continue;
-      const bool act = lane < m;
-      const int my = act ? (int)mem[lane] : (int)p0;
-      const Pt myc = coords_of(my, g);
-      const int col = colour_of(myc, ND);
-      bool settled = !act;
-      int round = 1;
-      for (; round <= cap; ++round) {
-        unsigned long long cm = 0;
-        for (int ph = 0; ph < pl.ncol; ++ph) {
-          // Jacobi within the phase: all evaluations read, then commit
+        if ((unsigned)tid < k1 - k0) {
+          sh.cflag[tid] = sh.msize[k0 + tid] ? 1u : 0u;
+          sh.crounds[tid] = 0;
+        }
+        if (tid == 0) sh.ncp = 0;
+        __syncthreads();
+        const bool act = (unsigned)tid < tot;
+        unsigned cl = 0;
+        while (act && cl + 1 < k1 - k0 && sh.off[cl + 1] <= (unsigned)tid) ++cl;
+        const int my = act ? (int)sh.memb[k0 + cl][tid - sh.off[cl]] : 0;
+        const Pt myc = coords_of(my, g);
+        const int col = colour_of(myc, ND);
+        bool settled = !act;
+        int round = 1;
+        for (; round <= cap; ++round) {
+          // every unsettled member is evaluated on the field as the round
+          // starts; an evaluation depends only on its read set, so it is
+          // redone at the member's phase only if a commit earlier in the
+          // round landed there (dirty)
+          const bool live = act && (sh.cflag[cl] & 1u);
           int res = 0;
           float v = 0.0f;
-          if (!settled && col == ph) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
-          if (res != 0) settled = true;
-          if (res == 2) a.out[my] = v;
-          const unsigned long long pm = __ballot(res == 2);
-          cm |= pm;
-          if (pm) __threadfence_block();
+          if (live && !settled) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
+          bool dirty = false;
+          for (int ph = 0; ph < pl.ncol; ++ph) {
+            const bool mine = live && !settled && col == ph;
+            if (__syncthreads_or(mine && dirty)) {
+              if (mine && dirty) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
+              __syncthreads();  // Jacobi: every evaluation of the phase reads before any commit
+            }
+            const bool commit = mine && res == 2;
+            if (mine && res != 0) settled = true;
+            if (commit) {
+              a.out[my] = v;
+              sh.cpts[atomicAdd(&sh.ncp, 1u)] = (unsigned)my;
+              atomicOr(&sh.cflag[cl], 2u);
+              ++commits;
+            }
+            __threadfence_block();
+            __syncthreads();
+            const unsigned ncp = sh.ncp;
+            for (unsigned j = 0; j < ncp; ++j) {
+              const Pt ck = coords_of((int)sh.cpts[j], g);
+              dirty |= H::reads(ck.x - myc.x, ck.y - myc.y, ck.z - myc.z);
+            }
+            __syncthreads();
+            if (tid == 0) sh.ncp = 0;
+          }
+          // a cluster stops at its first round without a commit
+          __syncthreads();
+          if ((unsigned)tid < k1 - k0) {
+            const unsigned f = sh.cflag[tid];
+            if ((f & 1u) && !(f & 2u)) {
+              sh.cflag[tid] = 0;
+              sh.crounds[tid] = (unsigned)round;
+            } else {
+              sh.cflag[tid] = f & 1u;
+            }
+          }
+          if (!__syncthreads_or((unsigned)tid < k1 - k0 && (sh.cflag[tid] & 1u))) break;
         }
-        commits += lane == 0 ? (unsigned)__popcll(cm) : 0u;
-        if (!cm) break;
+        if ((unsigned)tid < k1 - k0 && sh.msize[k0 + tid])
+          rounds = max(rounds, (sh.cflag[tid] & 1u) ? (unsigned)cap : sh.crounds[tid]);
+        __syncthreads();
+        k0 = k1;
       }
-      rounds = max(rounds, (unsigned)min(round, cap));
     }
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
+__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_cand[kCandMax];
-  __shared__ unsigned s_mem[4][kWaveCluster];
-  __shared__ unsigned s_nc, s_commits, s_rounds, s_ok;
+  __shared__ RefShared sh;
+  __shared__ unsigned s_commits, s_rounds, s_ok;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -1741,12 +1827,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
   if (c >= pl.nch) return;
   unsigned commits = 0, rounds = 0;
   switch (pl.ndim * 8 + pl.k) {
-    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
-    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
-    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
-    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
-    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
-    default: refine_chunk<3, 7>(a, pl, c, s_cand, s_nc, s_mem, commits, rounds); break;
+    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, c, sh, commits, rounds); break;
+    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, c, sh, commits, rounds); break;
+    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, c, sh, commits, rounds); break;
+    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, c, sh, commits, rounds); break;
+    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, c, sh, commits, rounds); break;
+    default: refine_chunk<3, 7>(a, pl, c, sh, commits, rounds); break;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -2153,7 +2239,7 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   ra.ws = (uint8_t*)d_ws;
   ra.status = d_status;
   ev_begin(4, s);
-  hipLaunchKernelGGL(refine_kernel, dim3(xcd_grid((int)nch)), dim3(256), 0, s, ra);
+  hipLaunchKernelGGL(refine_kernel, dim3(xcd_grid((int)nch)), dim3(kRefThreads), 0, s, ra);
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, ra);
   ev_end(4, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
