@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one VALU lane operation per lane per clock
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SHAPE = (1800, 3600)
 EB = 1e-3
 WORKLOAD = "1800x3600 float32 climate-grid field (64 plane waves |k|^-1.5 + N(0,1e-2^2) noise, seed 1), relative bound 1e-3"
@@ -37,9 +39,10 @@ def _src_hash():
     return h.hexdigest()
 
 
-def _traffic(kernel, per_launch_alg):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def _counters(kernel):
+    """The committed rocprofv3 counter summary of `kernel` on this workload
+    (HBM bytes per launch, VALU/SALU instructions), if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_1800x3600_rel1e-3.json" % kernel)
     if not os.path.exists(path):
         return None
@@ -49,7 +52,7 @@ def _traffic(kernel, per_launch_alg):
         return None
     if d.get("source_sha256") != _src_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def cpu_baseline(field, eb, target_s=10.0):
@@ -165,12 +168,26 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    def per_call(fn, calls=30):
+        """Durations (ms) of single calls, each bracketed by events on the
+        call's stream."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        for i in range(calls):
+            ev[i][0].record(stream)
+            fn(i % R)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        return {"p10_ms": round(float(np.percentile(t, 10)), 5), "p50_ms": round(float(np.median(t)), 5),
+                "p90_ms": round(float(np.percentile(t, 90)), 5)}
+
     t_wall0 = time.perf_counter()
     ms_step = timed(step, args.steps, args.warmup)
     t_wall = time.perf_counter() - t_wall0
     assert int(cst.item()) == 0 and int(dst.item()) == 0
     ms_comp = timed(comp, args.steps, args.warmup)
     ms_dec = timed(decomp, args.steps, args.warmup)
+    calls = {"compress": per_call(comp), "decompress": per_call(decomp)}
 
     # per-kernel durations: HIP events recorded by the library around each of
     # its kernels, on the call's stream
@@ -192,17 +209,35 @@ def main():
     s_gpu = outs[0][: slen[0]].cpu().numpy()
     rec_gpu = recs[0].cpu().numpy()
     stats = tsz.decompress_stats(ws)
+    from oracle import oracle as ora
     if args.no_cpu:
         cpu = None
         parity = None
-        from oracle import oracle as ora
-        ev = ora.eval_topology(field, rec_gpu)
     else:
         cpu, s_ref, rec_ref = cpu_baseline(field, EB)
         parity = bool(np.array_equal(s_gpu, s_ref) and
                       np.array_equal(rec_gpu.view(np.uint32), rec_ref.view(np.uint32)))
-        from oracle import oracle as ora
-        ev = ora.eval_topology(field, rec_gpu)
+    ev = ora.eval_topology(field, rec_gpu)
+
+    # the same field at the other two bounds: throughput and missed points
+    other = {}
+    for eb2 in (1e-2, 1e-4):
+        sz2 = torch.zeros(1, dtype=torch.int64, device=dev)
+        def comp2(k, eb2=eb2, sz2=sz2):
+            tsz.compress_async(ins[k], eb2, "rel", ws=ws, out=outs[k], size=sz2, status=cst)
+        tc2 = timed(comp2, max(10, args.steps // 2), 3)
+        torch.cuda.synchronize()
+        n2 = int(sz2.item())
+        def dec2(k, n2=n2):
+            tsz.decompress_async(outs[k], n2, recs[k], ws=ws, status=dst)
+        # every copy now holds this bound's stream (same field, same size)
+        td2 = timed(dec2, max(10, args.steps // 2), 3)
+        ok2 = int(cst.item()) == 0 and int(dst.item()) == 0
+        ev2 = ora.eval_topology(field, recs[0].cpu().numpy())
+        other["%g" % eb2] = {"compress_gbps": round(nbytes / (tc2 * 1e-3) / 1e9, 2),
+                             "decompress_gbps": round(nbytes / (td2 * 1e-3) / 1e9, 2),
+                             "ratio": round(nbytes / n2, 3), "status_ok": ok2,
+                             "missed_cps": {"FN": ev2["FN"], "FP": ev2["FP"], "FT": ev2["FT"]}}
 
     S = slen[0]
     # algorithmic bytes per launch: encode reads the field and writes the
@@ -213,9 +248,18 @@ def main():
     kernels = {k: {"ms": round(kms[k], 5),
                    "GBps": round(alg[k] / (kms[k] * 1e-3) / 1e9, 1) if k in alg and kms[k] > 0 else None}
                for k in names}
+    cnt = _counters(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": _traffic(dom, alg[dom])}
+                "traffic": cnt["bytes_per_launch"] if cnt else None,
+                "alg_bytes": alg[dom]}
+    valu = None
+    if cnt and cnt.get("valu_per_launch"):
+        ops = cnt["valu_per_launch"] * 64
+        valu = {"kernel": dom, "lane_ops_per_elem": round(ops / n, 1),
+                "achieved": round(ops / (kms[dom] * 1e-3) / 1e12, 2), "peak": VALU_PEAK_TOPS,
+                "unit": "T lane-ops/s", "frac": round(ops / (kms[dom] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+                "salu_per_launch": cnt.get("salu_per_launch")}
     value = nbytes / (ms_step * 1e-3) / 1e9
     line = {
         "metric": "compress/decompress GB/s at rel eb 1e-3; missed CPs; serve p50/p99 latency",
@@ -242,8 +286,11 @@ def main():
                        "FN_extrema": ev["FN_min"] + ev["FN_max"]},
         "max_err_over_e": None,
         "refine": stats,
+        "calls": calls,
         "kernels": kernels,
         "roofline": roofline,
+        "valu": valu,
+        "other_bounds": other,
         "cpu_baseline": cpu,
         "parity_with_oracle": parity,
         "wall_s_timed_loop": round(t_wall, 3),
