@@ -313,20 +313,17 @@ __device__ __forceinline__ int encode_block(int v, int lane, unsigned* dst,
   return w;
 }
 
-// Inverse: lane j < w loads plane j; each plane is then broadcast with
-// readlane and every lane takes its own bit; signed residuals; in-wave
-// inclusive prefix sum.
+// Inverse: each lane reads its own 32-bit half of every plane (lanes 0-31
+// the low word, 32-63 the high word) and takes its bit; signed residuals;
+// in-wave inclusive prefix sum.
 template <typename PlanePtr>
 __device__ __forceinline__ int decode_block(PlanePtr planes, int w, int first, unsigned long long sign,
                                             int lane) {
-  const unsigned long long mine = lane < w ? planes[lane] : 0ull;
-  const int lo = (int)(unsigned)mine, hi = (int)(unsigned)(mine >> 32);
+  const auto pw = reinterpret_cast<const unsigned*>(planes) + (lane >> 5);
+  const unsigned sh = (unsigned)lane & 31u;
   unsigned mag = 0;
-  for (int j = 0; j < w; ++j) {
-    const unsigned long long pj = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane(hi, j) << 32) |
-                                  (unsigned)__builtin_amdgcn_readlane(lo, j);
-    mag |= (unsigned)((pj >> lane) & 1ull) << j;
-  }
+#pragma unroll 4
+  for (int j = 0; j < w; ++j) mag |= ((pw[2 * j] >> sh) & 1u) << j;
   int r = ((sign >> lane) & 1ull) ? (int)(0u - mag) : (int)mag;
   if (lane == 0) r = first;
   return wave_incl_scan(r, lane);
@@ -1469,6 +1466,25 @@ struct Around {
   }
 };
 
+// True if every point within two rows/planes (and two columns) of p lies in
+// the array: then the row spans below can be loaded whole.  Only points
+// near the first or last rows of the field fail this.
+template <int ND>
+__device__ __forceinline__ bool far_from_ends(int p, const GeomD& g) {
+  const int reachf = (ND == 3 ? 3 * g.nxy : 0) + 3 * g.nx + 3;
+  return p >= reachf && p < g.n - reachf;
+}
+
+// Bits [lo, lo + 31] of the queued-saddle bitmap (lo >= 0), from the two
+// words holding bit lo.  The second word may lie past the bitmap's last word
+// (still inside the workspace); its bits are then never used.
+__device__ __forceinline__ unsigned bm_span(const unsigned long long* bm, int lo) {
+  unsigned long long w[2];
+  __builtin_memcpy(w, bm + (lo >> 6), sizeof(w));
+  const int sh = lo & 63;
+  return (unsigned)(sh ? (w[0] >> sh) | (w[1] << (64 - sh)) : w[0]);
+}
+
 // One evaluation of the queued saddle p on the current field: 0 reject,
 // 1 already a saddle, 2 accept (value in *vout).  The cells the
 // classifications read (L1 distance <= 2) are loaded in one batch and kept in
@@ -1482,16 +1498,30 @@ __device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels,
   const GeomD& g = pl.g;
   const Around<ND, K> ar(c, g);
   float v[2 * CZ + 1][5][5];
+  if (far_from_ends<ND>(p, g)) {
+    // one vector load per row of the core (every span lies inside the
+    // array); rows outside the grid read p's own row instead
 #pragma unroll
-  for (int dz = -CZ; dz <= CZ; ++dz)
+    for (int dz = -CZ; dz <= CZ; ++dz)
 #pragma unroll
-    for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) {
-        if (Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) > 2) continue;
-        const int q = ar.in(dx, dy, dz) ? p + dz * g.nxy + dy * g.nx + dx : p;
-        v[dz + CZ][dy + 2][dx + 2] = fld[q];
+      for (int dy = -2; dy <= 2; ++dy) {
+        const int sp = 2 - Hood<ND, K>::iabs(dy) - Hood<ND, K>::iabs(dz);
+        if (sp < 0) continue;
+        const int q0 = ar.in(0, dy, dz) ? p + dz * g.nxy + dy * g.nx : p;
+        __builtin_memcpy(&v[dz + CZ][dy + 2][2 - sp], fld + (q0 - sp), sizeof(float) * (2 * sp + 1));
       }
+  } else {
+#pragma unroll
+    for (int dz = -CZ; dz <= CZ; ++dz)
+#pragma unroll
+      for (int dy = -2; dy <= 2; ++dy)
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+          if (Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) > 2) continue;
+          const int q = ar.in(dx, dy, dz) ? p + dz * g.nxy + dy * g.nx + dx : p;
+          v[dz + CZ][dy + 2][dx + 2] = fld[q];
+        }
+  }
   constexpr int U[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
   int lab[6];
 #pragma unroll
@@ -1587,6 +1617,34 @@ __device__ __forceinline__ void reach(const unsigned long long* bm, int p, Pt c,
   using H = Hood<ND, K>;
   const Around<ND, K> ar(c, g);
   any = smaller = false;
+  if (far_from_ends<ND>(p, g) && H::R <= 3) {
+    // one two-word load per row of the read set
+    auto plane = [&](int dz) {
+#pragma unroll
+      for (int dy = -H::R; dy <= H::R; ++dy) {
+        unsigned rm = 0, lm = 0;  // read-set cells of the row (bit dx + R), those left of p
+#pragma unroll
+        for (int dx = -H::R; dx <= H::R; ++dx)
+          if (H::read(dx, dy, dz) && !(dx == 0 && dy == 0 && dz == 0)) {
+            if (ar.in(dx, dy, dz)) rm |= 1u << (dx + H::R);
+            if (dx < 0) lm |= 1u << (dx + H::R);
+          }
+        if (!rm) continue;
+        const unsigned bits = bm_span(bm, p + dz * g.nxy + dy * g.nx - H::R) & rm;
+        any |= bits != 0;
+        if (dz < 0 || (dz == 0 && dy < 0)) smaller |= bits != 0;
+        if (dz == 0 && dy == 0) smaller |= (bits & lm) != 0;
+      }
+    };
+    if constexpr (ND == 3 && K == 7) {
+#pragma unroll 1
+      for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+    } else {
+#pragma unroll
+      for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+    }
+    return;
+  }
   auto plane = [&](int dz) {
 #pragma unroll
     for (int dy = -H::R; dy <= H::R; ++dy)
@@ -1645,22 +1703,39 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
     const int cur = (int)mem[head];
     const Pt cc = coords_of(cur, g);
     const Around<ND, K> ar(cc, g);
+    const bool far = far_from_ends<ND>(cur, g);
+    auto add = [&](int q) {
+      bool seen = false;
+      for (unsigned j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
+      if (seen) return;
+      if ((unsigned)q < p0) owner = false;
+      if (m == (unsigned)kClusterMax) *over = true;
+      else mem[m++] = (unsigned)q;
+    };
     auto plane = [&](int dz) {
 #pragma unroll
-      for (int dy = -H::R; dy <= H::R; ++dy)
+      for (int dy = -H::R; dy <= H::R; ++dy) {
+        if (far) {
+          // the row's queued cells from one two-word load
+          unsigned rm = 0;
 #pragma unroll
-        for (int dx = -H::R; dx <= H::R; ++dx) {
-          if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
-          const bool in = ar.in(dx, dy, dz);
-          const int q = in ? cur + dz * g.nxy + dy * g.nx + dx : cur;
-          if (!(in && ((bm[q >> 6] >> (q & 63)) & 1ull))) continue;
-          bool seen = false;
-          for (unsigned j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
-          if (seen) continue;
-          if ((unsigned)q < p0) owner = false;
-          if (m == (unsigned)kClusterMax) *over = true;
-          else mem[m++] = (unsigned)q;
+          for (int dx = -H::R; dx <= H::R; ++dx)
+            if (H::read(dx, dy, dz) && !(dx == 0 && dy == 0 && dz == 0) && ar.in(dx, dy, dz))
+              rm |= 1u << (dx + H::R);
+          if (!rm) continue;
+          const int row = cur + dz * g.nxy + dy * g.nx;
+          for (unsigned bits = bm_span(bm, row - H::R) & rm; bits; bits &= bits - 1)
+            add(row + __builtin_ctz(bits) - H::R);
+        } else {
+#pragma unroll
+          for (int dx = -H::R; dx <= H::R; ++dx) {
+            if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
+            const bool in = ar.in(dx, dy, dz);
+            const int q = in ? cur + dz * g.nxy + dy * g.nx + dx : cur;
+            if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q);
+          }
         }
+      }
     };
     if constexpr (ND == 3 && K == 7) {
 #pragma unroll 1
