@@ -143,6 +143,66 @@ int toposzp_decompress_sync(const uint8_t *d_in, size_t in_size, float *d_out,
                             size_t out_cap_elems, void *d_ws, size_t ws_bytes,
                             void *stream);
 
+/* ---- Batched form: many fields of uneven sizes per call (one launch per
+ * stage for the whole batch; every field's stream and reconstruction are
+ * those of a one-field call).  Job arrays are host arrays of `count`
+ * entries (1..4096), read during the call only; every pointer inside a job
+ * is a device pointer with the alignment of the one-field calls.  The
+ * workspace (sized by the *_workspace_size calls, cleared once with
+ * toposzp_workspace_init) holds a job table and one workspace per job; a
+ * batch call copies the table into it on `stream`.  Host-detected errors in
+ * any job fail the whole call before anything is enqueued; device-side
+ * results and errors go to each job's own size/status. */
+typedef struct {
+  const float *d_field; /* N float32 values, C order */
+  uint32_t ndim;        /* 2 or 3 */
+  uint64_t dims[3];     /* C order; unused entries ignored */
+  int32_t eb_mode;      /* TOPOSZP_EB_ABS or TOPOSZP_EB_REL */
+  double eb;
+  uint8_t *d_out;       /* out_cap >= toposzp_compress_bound(ndim, dims) */
+  size_t out_cap;
+  uint64_t *d_out_size; /* device uint64: stream length */
+  int32_t *d_status;    /* device int32: status of this job */
+} toposzp_compress_job;
+
+typedef struct {
+  const uint8_t *d_in; /* stream */
+  size_t in_size;
+  float *d_out;        /* reconstruction, out_cap_elems values */
+  size_t out_cap_elems;
+  int32_t *d_status;   /* device int32: status of this job */
+} toposzp_decompress_job;
+
+size_t toposzp_compress_batch_workspace_size(uint32_t count, const toposzp_compress_job *h_jobs);
+size_t toposzp_decompress_batch_workspace_size(uint32_t count, const toposzp_decompress_job *h_jobs);
+int toposzp_compress_batch(uint32_t count, const toposzp_compress_job *h_jobs, const toposzp_params *params,
+                           void *d_ws, size_t ws_bytes, void *stream);
+int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job *h_jobs, void *d_ws, size_t ws_bytes,
+                             void *stream);
+/* Counters (as toposzp_decompress_stats) of job `index` of the last batched
+ * decompression on this workspace with these jobs. */
+int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job *h_jobs, const void *d_ws,
+                                   uint32_t index, int64_t out[5], void *stream);
+
+/* Launch shapes used by every call of this process (they change no byte of
+ * any result): waves per workgroup of the encode and decode kernels (4 or 8)
+ * and the persistent grid of the batched form in workgroups per compute
+ * unit (1..32).  Defaults {4, 4, 8, 8}. */
+typedef struct {
+  int32_t encode_waves, decode_waves, compress_wgs_per_cu, decompress_wgs_per_cu;
+} toposzp_tuning;
+int toposzp_set_tuning(const toposzp_tuning *t);
+int toposzp_get_tuning(toposzp_tuning *t);
+/* Autotuner: runs the given batch under each candidate shape (encode or
+ * decode waves x workgroups per CU), times it with HIP events on `stream`
+ * (synchronising it), keeps the fastest as the current tuning and returns it
+ * in *out.  The batch's outputs are written as by an ordinary call. */
+int toposzp_autotune_compress_batch(uint32_t count, const toposzp_compress_job *h_jobs,
+                                    const toposzp_params *params, void *d_ws, size_t ws_bytes, void *stream,
+                                    toposzp_tuning *out);
+int toposzp_autotune_decompress_batch(uint32_t count, const toposzp_decompress_job *h_jobs, void *d_ws,
+                                      size_t ws_bytes, void *stream, toposzp_tuning *out);
+
 /* Parses and checks a stream header held in host memory (at least 512
  * bytes, the header of d_in copied to the host).  Returns TOPOSZP_OK or
  * TOPOSZP_E_CORRUPT. */

@@ -21,6 +21,10 @@ SYMBOLS = [
     "toposzp_workspace_init", "toposzp_compress", "toposzp_decompress", "toposzp_compress_sync",
     "toposzp_decompress_sync", "toposzp_inspect", "toposzp_decompress_stats",
     "toposzp_set_timing", "toposzp_kernel_times",
+    "toposzp_compress_batch_workspace_size", "toposzp_decompress_batch_workspace_size",
+    "toposzp_compress_batch", "toposzp_decompress_batch", "toposzp_decompress_batch_stats",
+    "toposzp_set_tuning", "toposzp_get_tuning", "toposzp_autotune_compress_batch",
+    "toposzp_autotune_decompress_batch",
 ]
 
 
@@ -37,6 +41,25 @@ class Info(C.Structure):
                 ("rank_planes", C.c_uint64), ("eb", C.c_double), ("eps", C.c_double),
                 ("e", C.c_float), ("vmin", C.c_float), ("vmax", C.c_float),
                 ("sigma", C.c_float)]
+
+
+class CompressJob(C.Structure):
+    _fields_ = [("d_field", C.c_void_p), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
+                ("eb_mode", C.c_int32), ("eb", C.c_double), ("d_out", C.c_void_p),
+                ("out_cap", C.c_size_t), ("d_out_size", C.c_void_p), ("d_status", C.c_void_p)]
+
+
+class DecompressJob(C.Structure):
+    _fields_ = [("d_in", C.c_void_p), ("in_size", C.c_size_t), ("d_out", C.c_void_p),
+                ("out_cap_elems", C.c_size_t), ("d_status", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("encode_waves", C.c_int32), ("decode_waves", C.c_int32),
+                ("compress_wgs_per_cu", C.c_int32), ("decompress_wgs_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 _lib = None
@@ -80,6 +103,28 @@ def lib():
         L.toposzp_set_timing.argtypes = [C.c_int]
         L.toposzp_kernel_times.restype = C.c_int
         L.toposzp_kernel_times.argtypes = [C.POINTER(C.c_float), C.c_int]
+        cjp, djp = C.POINTER(CompressJob), C.POINTER(DecompressJob)
+        L.toposzp_compress_batch_workspace_size.restype = C.c_size_t
+        L.toposzp_compress_batch_workspace_size.argtypes = [C.c_uint32, cjp]
+        L.toposzp_decompress_batch_workspace_size.restype = C.c_size_t
+        L.toposzp_decompress_batch_workspace_size.argtypes = [C.c_uint32, djp]
+        L.toposzp_compress_batch.restype = C.c_int
+        L.toposzp_compress_batch.argtypes = [C.c_uint32, cjp, C.POINTER(Params), vp, C.c_size_t, vp]
+        L.toposzp_decompress_batch.restype = C.c_int
+        L.toposzp_decompress_batch.argtypes = [C.c_uint32, djp, vp, C.c_size_t, vp]
+        L.toposzp_decompress_batch_stats.restype = C.c_int
+        L.toposzp_decompress_batch_stats.argtypes = [C.c_uint32, djp, vp, C.c_uint32,
+                                                     C.POINTER(C.c_int64), vp]
+        L.toposzp_set_tuning.restype = C.c_int
+        L.toposzp_set_tuning.argtypes = [C.POINTER(Tuning)]
+        L.toposzp_get_tuning.restype = C.c_int
+        L.toposzp_get_tuning.argtypes = [C.POINTER(Tuning)]
+        L.toposzp_autotune_compress_batch.restype = C.c_int
+        L.toposzp_autotune_compress_batch.argtypes = [C.c_uint32, cjp, C.POINTER(Params), vp,
+                                                      C.c_size_t, vp, C.POINTER(Tuning)]
+        L.toposzp_autotune_decompress_batch.restype = C.c_int
+        L.toposzp_autotune_decompress_batch.argtypes = [C.c_uint32, djp, vp, C.c_size_t, vp,
+                                                        C.POINTER(Tuning)]
         _lib = L
     return _lib
 
@@ -228,3 +273,141 @@ def kernel_times():
     k = lib().toposzp_kernel_times(arr, 5)
     names = ["range", "encode", "finalize", "decode", "refine"]
     return {names[i]: float(arr[i]) for i in range(k)}
+
+
+# ---------------------------------------------------------------------------
+# Batched form.
+
+def get_tuning() -> dict:
+    t = Tuning()
+    lib().toposzp_get_tuning(C.byref(t))
+    return t.as_dict()
+
+
+def set_tuning(encode_waves=4, decode_waves=4, compress_wgs_per_cu=8, decompress_wgs_per_cu=8):
+    t = Tuning(int(encode_waves), int(decode_waves), int(compress_wgs_per_cu), int(decompress_wgs_per_cu))
+    rc = lib().toposzp_set_tuning(C.byref(t))
+    if rc != OK:
+        raise ValueError(f"toposzp_set_tuning: {strerror(rc)}")
+
+
+class CompressBatch:
+    """Compression of several float32 CUDA fields in one batched call.
+
+    fields: list of contiguous float32 CUDA tensors (2D or 3D); ebs: one bound
+    per field; modes: "rel"/"abs" per field (or one for all).  Output buffers,
+    sizes, statuses and the workspace are allocated once here and reused by
+    every run()."""
+
+    def __init__(self, fields, ebs, modes="rel", device=None, **params):
+        import torch
+        n = len(fields)
+        if n < 1:
+            raise ValueError("empty batch")
+        if isinstance(modes, str):
+            modes = [modes] * n
+        self.fields = list(fields)
+        device = device or self.fields[0].device
+        self.outs, self.caps = [], []
+        self.sizes = torch.zeros(n, dtype=torch.int64, device=device)
+        self.status = torch.zeros(n, dtype=torch.int32, device=device)
+        self.jobs = (CompressJob * n)()
+        for i, f in enumerate(self.fields):
+            if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous() or f.dim() not in (2, 3):
+                raise TypeError("fields must be contiguous 2D/3D float32 CUDA tensors")
+            cap = compress_bound(tuple(f.shape))
+            out = torch.empty(cap, dtype=torch.uint8, device=device)
+            self.outs.append(out)
+            j = self.jobs[i]
+            j.d_field = f.data_ptr()
+            j.ndim = f.dim()
+            j.dims = _dims(tuple(f.shape))
+            j.eb_mode = EB_REL if modes[i] == "rel" else EB_ABS
+            j.eb = float(ebs[i])
+            j.d_out = out.data_ptr()
+            j.out_cap = cap
+            j.d_out_size = self.sizes.data_ptr() + 8 * i
+            j.d_status = self.status.data_ptr() + 4 * i
+        self.params = _params(**params)
+        nbytes = int(lib().toposzp_compress_batch_workspace_size(n, self.jobs))
+        if nbytes == 0:
+            raise ValueError("invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        rc = lib().toposzp_workspace_init(C.c_void_p(self.ws.data_ptr()), nbytes, _stream(None))
+        if rc != OK:
+            raise RuntimeError(strerror(rc))
+
+    def run(self, stream=None):
+        rc = lib().toposzp_compress_batch(len(self.fields), self.jobs, C.byref(self.params),
+                                          C.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream))
+        if rc != OK:
+            raise RuntimeError(f"toposzp_compress_batch: {strerror(rc)} ({rc})")
+
+    def autotune(self, stream=None) -> dict:
+        t = Tuning()
+        rc = lib().toposzp_autotune_compress_batch(len(self.fields), self.jobs, C.byref(self.params),
+                                                   C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                   _stream(stream), C.byref(t))
+        if rc != OK:
+            raise RuntimeError(f"toposzp_autotune_compress_batch: {strerror(rc)} ({rc})")
+        return t.as_dict()
+
+    def results(self):
+        """(statuses, [stream bytes views]) after the stream has been synchronised."""
+        st = self.status.cpu().tolist()
+        sz = self.sizes.cpu().tolist()
+        return st, [o[: int(z)] for o, z in zip(self.outs, sz)]
+
+
+class DecompressBatch:
+    """Decompression of several streams (uint8 CUDA tensors) into float32
+    CUDA tensors of the given shapes, in one batched call."""
+
+    def __init__(self, streams, shapes, device=None):
+        import torch
+        n = len(streams)
+        if n < 1 or len(shapes) != n:
+            raise ValueError("streams and shapes must be non-empty and of equal length")
+        device = device or streams[0].device
+        self.streams = list(streams)
+        self.recs = [torch.empty(tuple(sh), dtype=torch.float32, device=device) for sh in shapes]
+        self.status = torch.zeros(n, dtype=torch.int32, device=device)
+        self.jobs = (DecompressJob * n)()
+        for i, (sb, r) in enumerate(zip(self.streams, self.recs)):
+            j = self.jobs[i]
+            j.d_in = sb.data_ptr()
+            j.in_size = sb.numel()
+            j.d_out = r.data_ptr()
+            j.out_cap_elems = r.numel()
+            j.d_status = self.status.data_ptr() + 4 * i
+        nbytes = int(lib().toposzp_decompress_batch_workspace_size(n, self.jobs))
+        if nbytes == 0:
+            raise ValueError("invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        rc = lib().toposzp_workspace_init(C.c_void_p(self.ws.data_ptr()), nbytes, _stream(None))
+        if rc != OK:
+            raise RuntimeError(strerror(rc))
+
+    def run(self, stream=None):
+        rc = lib().toposzp_decompress_batch(len(self.streams), self.jobs, C.c_void_p(self.ws.data_ptr()),
+                                            self.ws.numel(), _stream(stream))
+        if rc != OK:
+            raise RuntimeError(f"toposzp_decompress_batch: {strerror(rc)} ({rc})")
+
+    def autotune(self, stream=None) -> dict:
+        t = Tuning()
+        rc = lib().toposzp_autotune_decompress_batch(len(self.streams), self.jobs,
+                                                     C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                     _stream(stream), C.byref(t))
+        if rc != OK:
+            raise RuntimeError(f"toposzp_autotune_decompress_batch: {strerror(rc)} ({rc})")
+        return t.as_dict()
+
+    def stats(self, index, stream=None):
+        arr = (C.c_int64 * 5)()
+        rc = lib().toposzp_decompress_batch_stats(len(self.streams), self.jobs, C.c_void_p(self.ws.data_ptr()),
+                                                  int(index), arr, _stream(stream))
+        if rc != OK:
+            raise RuntimeError(strerror(rc))
+        keys = ["rounds", "commits", "queued", "stencil_moves", "budget_skips"]
+        return {k: int(arr[i]) for i, k in enumerate(keys)}

@@ -38,6 +38,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "toposzp.h"
 
 // The compiler's lane-write intrinsic (v_writelane_b32): lane `l` (uniform)
@@ -428,7 +431,7 @@ __global__ void ws_init_kernel(uint8_t* ws, uint64_t nbytes) {
 // Relative-bound range pass: one partial (min key, max key, non-finite) per
 // workgroup; consumers reduce the partials.
 
-__global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f, int n, uint8_t* ws) {
+__device__ __forceinline__ void range_body(const float* __restrict__ f, int n, uint8_t* ws, int blk, int nblk) {
   __shared__ unsigned s_lo[4], s_hi[4], s_bad[4];
   float lo = INFINITY, hi = -INFINITY;
   bool bad = false;
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
   const float4* f4 = reinterpret_cast<const float4*>(f);
   // kRangeVec float4 per thread in flight at once; clamped indices repeat
   // the last vector, which changes neither extreme
-  for (int base = blockIdx.x * 256 * kRangeVec; base < n4; base += gridDim.x * 256 * kRangeVec) {
+  for (int base = blk * 256 * kRangeVec; base < n4; base += nblk * 256 * kRangeVec) {
     float4 v[kRangeVec];
 #pragma unroll
     for (int t = 0; t < kRangeVec; ++t) v[t] = f4[min(base + t * 256 + tid, n4 - 1)];
@@ -449,7 +452,7 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
       hi = fmaxf(hi, fmaxf(fmaxf(v[t].x, v[t].y), fmaxf(v[t].z, v[t].w)));
     }
   }
-  if (blockIdx.x == 0 && tid < n - 4 * n4) {
+  if (blk == 0 && tid < n - 4 * n4) {
     const float v = f[4 * n4 + tid];
     bad |= !(fabsf(v) <= FLT_MAX);
     lo = fminf(lo, v);
@@ -472,8 +475,12 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
     const uint4 part = {min(min(s_lo[0], s_lo[1]), min(s_lo[2], s_lo[3])),
                         max(max(s_hi[0], s_hi[1]), max(s_hi[2], s_hi[3])), s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3],
                         0u};
-    reinterpret_cast<uint4*>(ws + kPartOff)[blockIdx.x] = part;
+    reinterpret_cast<uint4*>(ws + kPartOff)[blk] = part;
   }
+}
+
+__global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f, int n, uint8_t* ws) {
+  range_body(f, n, ws, blockIdx.x, gridDim.x);
 }
 
 // Bound of the call (one wave): relative mode reduces the range partials.
@@ -551,21 +558,24 @@ __device__ __forceinline__ EncIn enc_fetch(const float* __restrict__ f, int b, i
   return r;
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
-  constexpr int WAVES = 4, BPW = kB / WAVES;  // blocks per wave
-  __shared__ unsigned s_pd[kB][2 * kMaxWData];
-  __shared__ unsigned s_pr[kB][2 * kMaxWRankBlk];
-  __shared__ unsigned long long s_sign[kB], s_rsign[kB];
-  __shared__ int s_first[kB], s_rfirst[kB];
-  __shared__ unsigned s_lab[kB * 4];
-  __shared__ int s_wd[kB], s_wr[kB];
-  __shared__ int s_pfd[kB + 1], s_pfr[kB + 1];
-  __shared__ float s_e;
-  __shared__ unsigned s_flags;
+// LDS of the encode kernel (one per workgroup, whatever the dimension).
+struct EncShared {
+  unsigned pd[kB][2 * kMaxWData];     // a block's data planes, 2 words each
+  unsigned pr[kB][2 * kMaxWRankBlk];  // its rank planes
+  unsigned long long sign[kB], rsign[kB];
+  int first[kB], rfirst[kB];
+  unsigned lab[kB * 4];
+  int wd[kB], wr[kB];
+  int pfd[kB + 1], pfr[kB + 1];
+  float e;
+  unsigned flags;
+};
 
-  const int c = xcd_chunk(blockIdx.x, a.nch);
-  if (c >= a.nch) return;
+// Encodes chunk c of the field of `a` (all WAVES waves of the workgroup).
+template <int ND, int WAVES>
+__device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& sh) {
+  constexpr int BPW = kB / WAVES;  // blocks per wave
+  static_assert(BPW % 4 == 0, "four blocks in flight per wave");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const GeomD& g = a.gd;
@@ -585,12 +595,12 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
     bool nf;
     call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
     if (lane == 0) {
-      s_e = e;
-      s_flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
+      sh.e = e;
+      sh.flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
     }
   }
   __syncthreads();
-  const float e = s_e;
+  const float e = sh.e;
   const double ed = (double)e;
   const float inv2e = 1.0f / (2.0f * e);
   const int n = g.n;
@@ -603,10 +613,10 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
     const int lb = b - c * kB;
     if (b >= a.nb) {  // past the end (last chunk only)
       if (lane == 0) {
-        s_wd[lb] = 0;
-        s_wr[lb] = 0;
+        sh.wd[lb] = 0;
+        sh.wr[lb] = 0;
       }
-      if (lane < 4) s_lab[4 * lb + lane] = 0;
+      if (lane < 4) sh.lab[4 * lb + lane] = 0;
       return;
     }
     const int b0 = b * kB;
@@ -704,11 +714,11 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
 
     unsigned long long sign;
     int first;
-    const int w = encode_block<kMaxWData, 5>(q, lane, s_pd[lb], sign, first, wover);
+    const int w = encode_block<kMaxWData, 5>(q, lane, sh.pd[lb], sign, first, wover);
     if (lane == 0) {
-      s_wd[lb] = w;
-      s_sign[lb] = sign;
-      s_first[lb] = first;
+      sh.wd[lb] = w;
+      sh.sign[lb] = sign;
+      sh.first[lb] = first;
     }
     if (topo) {
       // 2-bit labels: point i at byte i/4, bits 2(i%4); 16 points per dword
@@ -716,18 +726,18 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
       lab = lane_in(m_sad) ? CLS_SAD : lab;
       lab = lane_in(m_max) ? CLS_MAX : lab;
       const unsigned lv = row_or_last((unsigned)lab << lab_shift);
-      if ((lane & 15) == 15) s_lab[4 * lb + (lane >> 4)] = lv;
+      if ((lane & 15) == 15) sh.lab[4 * lb + (lane >> 4)] = lv;
       unsigned long long rsign;
       int rfirst;
       bool rover = false;
-      const int wr = encode_block<kMaxWRankBlk, 3>(delta, lane, s_pr[lb], rsign, rfirst, rover);
+      const int wr = encode_block<kMaxWRankBlk, 3>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
       if (lane == 0) {
-        s_wr[lb] = wr;
-        s_rsign[lb] = rsign;
-        s_rfirst[lb] = rfirst;
+        sh.wr[lb] = wr;
+        sh.rsign[lb] = rsign;
+        sh.rfirst[lb] = rfirst;
       }
     } else if (lane == 0) {
-      s_wr[lb] = 0;
+      sh.wr[lb] = 0;
     }
   };
 
@@ -746,7 +756,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
   }
   {
     const bool nf = nfm != 0, qo = qom != 0 || wover;
-    if (lane == 0 && (nf || qo)) atomicOr(&s_flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
+    if (lane == 0 && (nf || qo)) atomicOr(&sh.flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
   }
   __syncthreads();
 
@@ -758,17 +768,18 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
     const int b = c * kB + lb;
     if (b < a.nb) {
       if (part == 0) {
-        out[a.off[S2] + b] = (uint8_t)s_wd[lb];
-        *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = s_sign[lb];
-        *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = s_first[lb];
+        out[a.off[S2] + b] = (uint8_t)sh.wd[lb];
+        *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = sh.sign[lb];
+        *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = sh.first[lb];
       } else if (part == 1 && topo) {
-        out[a.off[R2] + b] = (uint8_t)s_wr[lb];
-        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = s_rsign[lb];
-        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = s_rfirst[lb];
+        out[a.off[R2] + b] = (uint8_t)sh.wr[lb];
+        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = sh.rsign[lb];
+        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = sh.rfirst[lb];
       }
     }
-    if (topo && c * kB + (tid >> 2) < a.nb)
-      *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)(c * kB) + 4 * (size_t)tid) = s_lab[tid];
+    // the chunk's labels: 4 dwords per block, one per thread of the first 256
+    if (topo && tid < kB * 4 && c * kB + (tid >> 2) < a.nb)
+      *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)(c * kB) + 4 * (size_t)tid) = sh.lab[tid];
   }
 
   // chunk: constant-block bitmaps, local prefix of widths, chunk totals
@@ -776,47 +787,47 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
   if (wv == 0) {
     const int b = c * kB + lane;
     const bool bv = b < a.nb;
-    const int wd = s_wd[lane], wr = s_wr[lane];
+    const int wd = sh.wd[lane], wr = sh.wr[lane];
     const unsigned long long cb = __ballot(bv && wd == 0), cr = __ballot(bv && wr == 0);
     const int sd = wave_incl_scan(wd, lane), sr = wave_incl_scan(wr, lane);
-    s_pfd[lane + 1] = sd;
-    s_pfr[lane + 1] = sr;
+    sh.pfd[lane + 1] = sd;
+    sh.pfr[lane + 1] = sr;
     if (lane == 0) {
-      s_pfd[0] = 0;
-      s_pfr[0] = 0;
+      sh.pfd[0] = 0;
+      sh.pfr[0] = 0;
       *reinterpret_cast<unsigned long long*>(out + a.off[S1] + 8 * (size_t)c) = cb;
       if (topo) *reinterpret_cast<unsigned long long*>(out + a.off[R1] + 8 * (size_t)c) = cr;
     }
     if (lane == 63) {
       reinterpret_cast<unsigned*>(a.ws + L.tot_d)[c] = (unsigned)sd;
       reinterpret_cast<unsigned*>(a.ws + L.tot_r)[c] = (unsigned)sr;
-      reinterpret_cast<unsigned*>(a.ws + L.cflag)[c] = s_flags;
+      reinterpret_cast<unsigned*>(a.ws + L.cflag)[c] = sh.flags;
     }
   }
   __syncthreads();
 
   // this chunk's planes, compact, to its staging slot (coalesced from LDS)
   {
-    const int totd = 2 * s_pfd[kB];
+    const int totd = 2 * sh.pfd[kB];
     unsigned* dst = reinterpret_cast<unsigned*>(a.ws + L.stage_d) + (size_t)c * kB * 2 * kMaxWData;
     for (int o = tid; o < totd; o += WAVES * 64) {
-      int lo = 0, hi = kB;  // find lb with 2 s_pfd[lb] <= o < 2 s_pfd[lb+1]
+      int lo = 0, hi = kB;  // find lb with 2 sh.pfd[lb] <= o < 2 sh.pfd[lb+1]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (2 * s_pfd[mid] <= o) lo = mid; else hi = mid;
+        if (2 * sh.pfd[mid] <= o) lo = mid; else hi = mid;
       }
-      dst[o] = s_pd[lo][o - 2 * s_pfd[lo]];
+      dst[o] = sh.pd[lo][o - 2 * sh.pfd[lo]];
     }
     if (topo) {
-      const int totr = 2 * s_pfr[kB];
+      const int totr = 2 * sh.pfr[kB];
       unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * kMaxWRankBlk;
       for (int o = tid; o < totr; o += WAVES * 64) {
         int lo = 0, hi = kB;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (2 * s_pfr[mid] <= o) lo = mid; else hi = mid;
+          if (2 * sh.pfr[mid] <= o) lo = mid; else hi = mid;
         }
-        rdst[o] = s_pr[lo][o - 2 * s_pfr[lo]];
+        rdst[o] = sh.pr[lo][o - 2 * sh.pfr[lo]];
       }
     }
   }
@@ -828,8 +839,15 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs a) {
   }
 }
 
+template <int ND, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
+  __shared__ EncShared sh;
+  const int c = xcd_chunk(blockIdx.x, a.nch);
+  if (c < a.nch) encode_body<ND, WAVES>(a, c, sh);
+}
+
 // Exclusive scan of the chunk plane totals (in place), flags, and the bound.
-__global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
+__device__ __forceinline__ void scan_body(const ScanArgs& a) {
   __shared__ unsigned long long s_w[2][16];
   __shared__ unsigned long long s_carry[2];
   __shared__ unsigned s_fl;
@@ -904,6 +922,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) { scan_body(a); }
+
 // ---------------------------------------------------------------------------
 // Finalize: payload placement, chunk index, header, status.
 
@@ -911,7 +931,8 @@ __device__ void put8(uint8_t* h, int off, uint64_t v) { memcpy(h + off, &v, 8); 
 __device__ void put4(uint8_t* h, int off, uint32_t v) { memcpy(h + off, &v, 4); }
 __device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); }
 
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+// Places chunk c's staged planes; the last chunk also writes the header.
+__device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   __shared__ uint8_t hdr[kHdr];
   __shared__ unsigned s_sa[4], s_sb[4];
   __shared__ unsigned s_red[5][4];
@@ -920,8 +941,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   __shared__ double s_eps;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int c = xcd_chunk(blockIdx.x, a.nch);  // same XCD as the chunk's encode
-  if (c >= a.nch) return;
   const bool last = c == a.nch - 1;  // writes the header
   const CompLayout L = comp_layout((uint64_t)a.nch);
   const unsigned* td = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
@@ -1095,6 +1114,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   for (int k = tid; k < kHdr; k += blockDim.x) a.out[k] = hdr[k];
 }
 
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+  const int c = xcd_chunk(blockIdx.x, a.nch);  // same XCD as the chunk's encode
+  if (c < a.nch) finalize_body(a, c);
+}
+
 // ---------------------------------------------------------------------------
 // Decompression.
 
@@ -1189,8 +1213,11 @@ __device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_c
   h->ok = (h->n <= out_cap) ? 1 : -1;
 }
 
-__global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
-  constexpr int WAVES = 4, BPW = kB / WAVES;
+// Decodes the chunk behind workgroup slot w_id (slots cover xcd_grid of the
+// capacity's chunk count; slot 0 also publishes the header verdict).
+template <int WAVES>
+__device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
+  constexpr int BPW = kB / WAVES;
   constexpr int kRankLds = kB * kMaxWRankBlk;  // rank planes staged when they fit
   __shared__ Hdr s_h;
   __shared__ uint64_t s_hb[kHdr / 8];
@@ -1205,7 +1232,6 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int w_id = blockIdx.x;
   if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, reinterpret_cast<uint8_t*>(s_hb), lane);
   if (tid == 0) {
     s_bad = 0;
@@ -1272,7 +1298,8 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
         s_rfirst[lb] = *reinterpret_cast<const int*>(a.in + h.off[R4] + 4 * b);
       }
     }
-    if (topo && (uint64_t)c * kB + (tid >> 2) < h.nb)
+    // the chunk's labels: 4 dwords per block, one per thread of the first 256
+    if (topo && tid < kB * 4 && (uint64_t)c * kB + (tid >> 2) < h.nb)
       s_lab[tid] = *reinterpret_cast<const unsigned*>(a.in + h.off[S6] + 16 * (uint64_t)c * kB + 4 * tid);
   }
   if (wv == 0) {
@@ -1412,6 +1439,11 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs a) {
     reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = s_skips;
     dflag[c] = s_corrupt;
   }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void decode_kernel(DecArgs a) {
+  decode_body<WAVES>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1883,9 +1915,9 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
   }
 }
 
-__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
+// Refines the queued saddles of the chunk behind workgroup slot w_id.
+__device__ __forceinline__ void refine_body(const RefArgs& a, int w_id, RefShared& sh) {
   __shared__ Plan s_p;
-  __shared__ RefShared sh;
   __shared__ unsigned s_commits, s_rounds, s_ok;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
@@ -1897,8 +1929,8 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
   }
   __syncthreads();
   const Plan& pl = s_p;
-  if (!s_ok || (int)blockIdx.x >= xcd_grid(pl.nch)) return;
-  const int c = xcd_chunk(blockIdx.x, pl.nch);
+  if (!s_ok || w_id >= xcd_grid(pl.nch)) return;
+  const int c = xcd_chunk(w_id, pl.nch);
   if (c >= pl.nch) return;
   unsigned commits = 0, rounds = 0;
   switch (pl.ndim * 8 + pl.k) {
@@ -1924,6 +1956,11 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
     if (s_commits) atomicAdd(&sp->commits, s_commits);
     atomicMax(&sp->rounds, s_rounds);
   }
+}
+
+__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
+  __shared__ RefShared sh;
+  refine_body(a, blockIdx.x, sh);
 }
 
 // Whole-field replay of the schedule over every queued saddle, by one
@@ -1993,7 +2030,7 @@ __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout
 
 // Status and counters of the decompression (one workgroup), after the
 // whole-field replay when a cluster needed it.
-__global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
+__device__ __forceinline__ void tail_body(const RefArgs& a) {
   __shared__ Plan s_p;
   __shared__ unsigned s_big, s_ok, s_hf, s_fl, s_rounds;
   __shared__ unsigned long long s_sum[4];
@@ -2079,6 +2116,133 @@ __global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) { tail_body(a); }
+
+// ---------------------------------------------------------------------------
+// Batched form: many fields (or streams) in one launch per stage.  A table
+// of per-field kernel arguments sits at the head of the workspace; a
+// persistent grid walks the (field, chunk) items, each XCD taking a
+// contiguous range of them, and runs the same bodies as the one-field
+// kernels, so every field's bytes are those of a one-field call.
+
+constexpr int kBatchMax = 4096;
+
+struct CompJob {
+  EncArgs enc;
+  FinArgs fin;
+  ScanArgs scan;
+  int ndim, nrange;
+};
+struct DecJob {
+  DecArgs dec;
+  RefArgs ref;
+};
+struct BatchHdr {
+  int count, n_range, n_chunk, n_slot;
+};
+// Table: BatchHdr, int pre_a[count + 1], int pre_b[count + 1], then the jobs
+// (16-byte aligned).  Compression: pre_a over range items, pre_b over chunks;
+// decompression: pre_a over decode/refine slots.
+__host__ __device__ inline size_t tab_jobs_off(int count) {
+  return (sizeof(BatchHdr) + 2 * sizeof(int) * (size_t)(count + 1) + 15) & ~size_t(15);
+}
+
+// Field owning `item`: the largest f with pre[f] <= item (empty fields skipped).
+__device__ __forceinline__ int find_job(const int* pre, int count, int item) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Items [0, T) over a grid of a multiple of 8 workgroups: XCD x (= workgroup
+// mod 8) takes the x-th eighth of the items, its workgroups in turn.
+template <typename Fn>
+__device__ __forceinline__ void for_items(int T, Fn&& fn) {
+  const int gx = (int)gridDim.x >> 3, x = (int)blockIdx.x & 7, j = (int)blockIdx.x >> 3;
+  const int per = (T + 7) >> 3;
+  const int end = min((x + 1) * per, T);
+  for (int i = x * per + j; i < end; i += gx) {
+    fn(i);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void range_batch_kernel(const uint8_t* tab) {
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
+  const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->n_range, [&](int it) {
+    const int f = find_job(pre, h->count, it);
+    const CompJob& J = jobs[f];
+    range_body(J.enc.f, J.enc.gd.n, J.enc.ws, it - pre[f], J.nrange);
+  });
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t* tab) {
+  __shared__ EncShared sh;
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr)) + h->count + 1;
+  const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->n_chunk, [&](int it) {
+    const int f = find_job(pre, h->count, it);
+    const CompJob& J = jobs[f];
+    if (J.ndim == 3) encode_body<3, WAVES>(J.enc, it - pre[f], sh);
+    else encode_body<2, WAVES>(J.enc, it - pre[f], sh);
+  });
+}
+
+__global__ __launch_bounds__(1024) void scan_batch_kernel(const uint8_t* tab) {
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->count, [&](int f) {
+    if (!jobs[f].fin.fused) scan_body(jobs[f].scan);
+  });
+}
+
+__global__ __launch_bounds__(256) void finalize_batch_kernel(const uint8_t* tab) {
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr)) + h->count + 1;
+  const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->n_chunk, [&](int it) {
+    const int f = find_job(pre, h->count, it);
+    finalize_body(jobs[f].fin, it - pre[f]);
+  });
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void decode_batch_kernel(const uint8_t* tab) {
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
+  const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->n_slot, [&](int it) {
+    const int f = find_job(pre, h->count, it);
+    decode_body<WAVES>(jobs[f].dec, it - pre[f]);
+  });
+}
+
+__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_batch_kernel(
+    const uint8_t* tab) {
+  __shared__ RefShared sh;
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
+  const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->n_slot, [&](int it) {
+    const int f = find_job(pre, h->count, it);
+    refine_body(jobs[f].ref, it - pre[f], sh);
+  });
+}
+
+__global__ __launch_bounds__(1024) void tail_batch_kernel(const uint8_t* tab) {
+  const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
+  const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
+  for_items(h->count, [&](int f) { tail_body(jobs[f].ref); });
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -2144,6 +2308,221 @@ void ev_end(int k, hipStream_t s) {
   g_ev_used[k] = true;
 }
 
+size_t ws_need_n(uint64_t n) {
+  const uint64_t nb = (n + kB - 1) / kB, nch = (nb + kB - 1) / kB;
+  const uint64_t c = comp_layout(nch).end, d = dec_layout(nb, nch).end;
+  return (size_t)al256(c > d ? c : d);
+}
+
+// Launch shapes (they change no byte of any result).
+toposzp_tuning g_tune = {4, 4, 8, 8};
+
+bool tuning_ok(const toposzp_tuning& t) {
+  auto wgs = [](int v) { return v >= 1 && v <= 32; };
+  return (t.encode_waves == 4 || t.encode_waves == 8) && (t.decode_waves == 4 || t.decode_waves == 8) &&
+         wgs(t.compress_wgs_per_cu) && wgs(t.decompress_wgs_per_cu);
+}
+
+int g_cus[64];
+int cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!g_cus[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+    g_cus[dev] = c;
+  }
+  return g_cus[dev];
+}
+
+// Persistent grid: wgs_per_cu workgroups per CU, a multiple of 8, at most
+// what the items need (rounded up to 8).
+unsigned batch_grid(int items, int wgs_per_cu) {
+  long long g = (long long)cu_count() * wgs_per_cu;
+  const long long need = ((long long)items + 7) / 8 * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  return (unsigned)((g + 7) / 8 * 8);
+}
+
+// Checks one compression request and fills its kernel arguments.
+int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode, double eb,
+               const toposzp_params* params, uint8_t* d_ws, size_t ws_bytes, uint8_t* d_out, size_t out_cap,
+               uint64_t* d_out_size, int32_t* d_status, CompJob* J) {
+  toposzp_params p = {64, 0, 0, 16, 1};
+  if (params) p = *params;
+  HostGeom hg;
+  int rc = host_geom(ndim, dims, &hg);
+  if (rc != TOPOSZP_OK) return rc;
+  if (!d_field || !d_ws || !d_out || !d_out_size || !d_status) return TOPOSZP_E_INVALID_ARG;
+  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_out & 7) ||
+      ((uintptr_t)d_out_size & 7) || ((uintptr_t)d_status & 3))
+    return TOPOSZP_E_INVALID_ARG;
+  if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != TOPOSZP_EB_ABS && eb_mode != TOPOSZP_EB_REL))
+    return TOPOSZP_E_INVALID_ARG;
+  if (p.block != (uint32_t)kB || (p.topo != 0 && p.topo != 1) || (p.rank_scope != 0 && p.rank_scope != 1) ||
+      (p.rbf_policy != 0 && p.rbf_policy != 1) || p.max_rounds < 1 || p.max_rounds > kMaxRounds)
+    return TOPOSZP_E_INVALID_ARG;
+  if (p.rank_scope == 1 && p.topo) return TOPOSZP_E_UNSUPPORTED;
+  if (out_cap < toposzp_compress_bound(ndim, dims)) return TOPOSZP_E_CAPACITY;
+  if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
+
+  int nrange = (int)((hg.g.n / 4 + 256 * kRangeVec - 1) / (256 * kRangeVec));
+  if (nrange > kRangeWG) nrange = kRangeWG;
+  if (nrange < 1) nrange = 1;
+  const float e_abs = host_round_down(eb);
+
+  EncArgs& ea = J->enc;
+  ea.f = d_field;
+  ea.out = d_out;
+  ea.ws = d_ws;
+  ea.gd.n = hg.g.n;
+  ea.gd.nx = hg.g.nx;
+  ea.gd.ny = hg.g.ny;
+  ea.gd.nz = hg.g.nz;
+  ea.gd.nxy = hg.g.nx * hg.g.ny;
+  ea.gd.dx = make_div((unsigned)hg.g.nx);
+  ea.gd.dy = make_div((unsigned)hg.g.ny);
+  ea.nb = (int)hg.nb;
+  ea.nch = (int)hg.nch;
+  ea.topo = p.topo;
+  ea.eb_mode = eb_mode;
+  ea.nrange = nrange;
+  ea.eb = eb;
+  ea.e_abs = e_abs;
+  seg_layout(hg.nb, p.topo, 0, 0, ea.off, ea.len);
+
+  ScanArgs& sa = J->scan;
+  sa.ws = d_ws;
+  sa.nch = ea.nch;
+  sa.eb_mode = eb_mode;
+  sa.nrange = nrange;
+  sa.eb = eb;
+  sa.e_abs = e_abs;
+
+  FinArgs& fa = J->fin;
+  fa.out = d_out;
+  fa.ws = d_ws;
+  fa.out_size = d_out_size;
+  fa.status = d_status;
+  fa.g = hg.g;
+  for (int d = 0; d < 3; ++d) fa.dims[d] = hg.dims[d];
+  fa.nb = ea.nb;
+  fa.nch = ea.nch;
+  fa.topo = p.topo;
+  fa.eb_mode = eb_mode;
+  fa.rbf_policy = p.rbf_policy;
+  fa.max_rounds = p.max_rounds;
+  fa.eb = eb;
+  fa.e_abs = e_abs;
+  fa.nrange = nrange;
+  fa.fused = ea.nch <= kFuseMax ? 1 : 0;
+  memcpy(fa.off, ea.off, sizeof(ea.off));
+  memcpy(fa.len, ea.len, sizeof(ea.len));
+  const double sig[3] = {0.5, 0.75, 1.0};
+  for (int t = 0; t < 3; ++t)
+    for (int d2 = 0; d2 < 10; ++d2) fa.wtab[t][d2] = (float)exp(-(double)d2 / (2.0 * sig[t] * sig[t]));
+  J->ndim = (int)ndim;
+  J->nrange = eb_mode == TOPOSZP_EB_REL ? nrange : 0;
+  return TOPOSZP_OK;
+}
+
+// Checks one decompression request and fills its kernel arguments; *slots
+// receives the workgroup slots its capacity needs.
+int build_dec(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_elems, uint8_t* d_ws,
+              size_t ws_bytes, int32_t* d_status, DecJob* J, int* slots) {
+  if (!d_in || !d_out || !d_ws || !d_status || out_cap_elems < 1) return TOPOSZP_E_INVALID_ARG;
+  if (((uintptr_t)d_in & 7) || ((uintptr_t)d_out & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_status & 3))
+    return TOPOSZP_E_INVALID_ARG;
+  if (ws_bytes < kRegionOff + 4096) return TOPOSZP_E_CAPACITY;
+  uint64_t cap = out_cap_elems;
+  if (cap > (1ull << 31)) cap = (1ull << 31);
+  const uint64_t nch = ((cap + kB - 1) / kB + kB - 1) / kB;
+  DecArgs& da = J->dec;
+  da.in = d_in;
+  da.in_size = in_size;
+  da.out = d_out;
+  da.out_cap = out_cap_elems;
+  da.ws = d_ws;
+  da.ws_bytes = ws_bytes;
+  RefArgs& ra = J->ref;
+  ra.in = d_in;
+  ra.out = d_out;
+  ra.ws = d_ws;
+  ra.status = d_status;
+  *slots = xcd_grid((int)nch);
+  return TOPOSZP_OK;
+}
+
+void launch_encode(int ndim, int waves, unsigned grid, hipStream_t s, const EncArgs& ea) {
+  if (ndim == 3 && waves == 8) hipLaunchKernelGGL((encode_kernel<3, 8>), dim3(grid), dim3(512), 0, s, ea);
+  else if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4>), dim3(grid), dim3(256), 0, s, ea);
+  else if (waves == 8) hipLaunchKernelGGL((encode_kernel<2, 8>), dim3(grid), dim3(512), 0, s, ea);
+  else hipLaunchKernelGGL((encode_kernel<2, 4>), dim3(grid), dim3(256), 0, s, ea);
+}
+
+// Batch workspace: the table, then one single-field workspace per job.
+size_t comp_batch_layout(uint32_t count, const toposzp_compress_job* jobs, size_t* offs) {
+  size_t off = (size_t)al256(tab_jobs_off((int)count) + count * sizeof(CompJob));
+  for (uint32_t i = 0; i < count; ++i) {
+    HostGeom hg;
+    if (host_geom(jobs[i].ndim, jobs[i].dims, &hg) != TOPOSZP_OK) return 0;
+    if (offs) offs[i] = off;
+    off += ws_need(hg);
+  }
+  return off;
+}
+size_t dec_batch_layout(uint32_t count, const toposzp_decompress_job* jobs, size_t* offs) {
+  size_t off = (size_t)al256(tab_jobs_off((int)count) + count * sizeof(DecJob));
+  for (uint32_t i = 0; i < count; ++i) {
+    uint64_t cap = jobs[i].out_cap_elems;
+    if (cap < 1) return 0;
+    if (cap > (1ull << 31)) cap = 1ull << 31;
+    if (offs) offs[i] = off;
+    off += ws_need_n(cap);
+  }
+  return off;
+}
+
+// Times `run` (one enqueue of the batch) under each candidate tuning and
+// keeps the fastest: 2 untimed runs, then the median of 5 timed ones.
+template <typename Run>
+int autotune(const std::vector<toposzp_tuning>& cands, hipStream_t s, Run&& run, toposzp_tuning* out) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TOPOSZP_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TOPOSZP_E_DEVICE;
+  }
+  const toposzp_tuning saved = g_tune;
+  toposzp_tuning best = saved;
+  float best_ms = 1e30f;
+  int rc = TOPOSZP_OK;
+  for (const toposzp_tuning& t : cands) {
+    g_tune = t;
+    float ms[5];
+    for (int r = 0; r < 7 && rc == TOPOSZP_OK; ++r) {
+      if (r >= 2 && hipEventRecord(e0, s) != hipSuccess) rc = TOPOSZP_E_DEVICE;
+      if (rc == TOPOSZP_OK) rc = run();
+      if (rc == TOPOSZP_OK && r >= 2) {
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms[r - 2], e0, e1) != hipSuccess)
+          rc = TOPOSZP_E_DEVICE;
+      }
+    }
+    if (rc != TOPOSZP_OK) break;
+    std::sort(ms, ms + 5);
+    if (ms[2] < best_ms) {
+      best_ms = ms[2];
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tune = rc == TOPOSZP_OK ? best : saved;
+  if (out) *out = g_tune;
+  return rc;
+}
 
 }  // namespace
 
@@ -2193,131 +2572,189 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
                      double eb, const toposzp_params* params, void* d_ws, size_t ws_bytes,
                      uint8_t* d_out, size_t out_cap, uint64_t* d_out_size, int32_t* d_status,
                      void* stream) {
-  toposzp_params p = {64, 0, 0, 16, 1};
-  if (params) p = *params;
-  HostGeom hg;
-  int rc = host_geom(ndim, dims, &hg);
+  CompJob J;
+  const int rc = build_comp(d_field, ndim, dims, eb_mode, eb, params, (uint8_t*)d_ws, ws_bytes, d_out, out_cap,
+                            d_out_size, d_status, &J);
   if (rc != TOPOSZP_OK) return rc;
-  if (!d_field || !d_ws || !d_out || !d_out_size || !d_status) return TOPOSZP_E_INVALID_ARG;
-  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_out & 7) ||
-      ((uintptr_t)d_out_size & 7) || ((uintptr_t)d_status & 3))
-    return TOPOSZP_E_INVALID_ARG;
-  if (!(eb > 0.0) || !std::isfinite(eb) || (eb_mode != TOPOSZP_EB_ABS && eb_mode != TOPOSZP_EB_REL))
-    return TOPOSZP_E_INVALID_ARG;
-  if (p.block != (uint32_t)kB || (p.topo != 0 && p.topo != 1) || (p.rank_scope != 0 && p.rank_scope != 1) ||
-      (p.rbf_policy != 0 && p.rbf_policy != 1) || p.max_rounds < 1 || p.max_rounds > kMaxRounds)
-    return TOPOSZP_E_INVALID_ARG;
-  if (p.rank_scope == 1 && p.topo) return TOPOSZP_E_UNSUPPORTED;
-  if (out_cap < toposzp_compress_bound(ndim, dims)) return TOPOSZP_E_CAPACITY;
-  if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
-
-  int nrange = (int)((hg.g.n / 4 + 256 * kRangeVec - 1) / (256 * kRangeVec));
-  if (nrange > kRangeWG) nrange = kRangeWG;
-  if (nrange < 1) nrange = 1;
-  const float e_abs = host_round_down(eb);
-
-  EncArgs ea;
-  ea.f = d_field;
-  ea.out = d_out;
-  ea.ws = (uint8_t*)d_ws;
-  ea.gd.n = hg.g.n;
-  ea.gd.nx = hg.g.nx;
-  ea.gd.ny = hg.g.ny;
-  ea.gd.nz = hg.g.nz;
-  ea.gd.nxy = hg.g.nx * hg.g.ny;
-  ea.gd.dx = make_div((unsigned)hg.g.nx);
-  ea.gd.dy = make_div((unsigned)hg.g.ny);
-  ea.nb = (int)hg.nb;
-  ea.nch = (int)hg.nch;
-  ea.topo = p.topo;
-  ea.eb_mode = eb_mode;
-  ea.nrange = nrange;
-  ea.eb = eb;
-  ea.e_abs = e_abs;
-  seg_layout(hg.nb, p.topo, 0, 0, ea.off, ea.len);
-
-  ScanArgs sa;
-  sa.ws = (uint8_t*)d_ws;
-  sa.nch = ea.nch;
-  sa.eb_mode = eb_mode;
-  sa.nrange = nrange;
-  sa.eb = eb;
-  sa.e_abs = e_abs;
-
-  FinArgs fa;
-  fa.out = d_out;
-  fa.ws = (uint8_t*)d_ws;
-  fa.out_size = d_out_size;
-  fa.status = d_status;
-  fa.g = hg.g;
-  for (int d = 0; d < 3; ++d) fa.dims[d] = hg.dims[d];
-  fa.nb = ea.nb;
-  fa.nch = ea.nch;
-  fa.topo = p.topo;
-  fa.eb_mode = eb_mode;
-  fa.rbf_policy = p.rbf_policy;
-  fa.max_rounds = p.max_rounds;
-  fa.eb = eb;
-  fa.e_abs = e_abs;
-  fa.nrange = nrange;
-  fa.fused = ea.nch <= kFuseMax ? 1 : 0;
-  memcpy(fa.off, ea.off, sizeof(ea.off));
-  memcpy(fa.len, ea.len, sizeof(ea.len));
-  const double sig[3] = {0.5, 0.75, 1.0};
-  for (int t = 0; t < 3; ++t)
-    for (int d2 = 0; d2 < 10; ++d2) fa.wtab[t][d2] = (float)exp(-(double)d2 / (2.0 * sig[t] * sig[t]));
-
+  const EncArgs& ea = J.enc;
   for (int k = 0; k < 3; ++k) g_ev_used[k] = false;
   if (eb_mode == TOPOSZP_EB_REL) {
     ev_begin(0, s);
-    hipLaunchKernelGGL(range_kernel, dim3(nrange), dim3(256), 0, s, d_field, hg.g.n, (uint8_t*)d_ws);
+    hipLaunchKernelGGL(range_kernel, dim3(ea.nrange), dim3(256), 0, s, d_field, ea.gd.n, (uint8_t*)d_ws);
     ev_end(0, s);
   }
   ev_begin(1, s);
-  if (hg.g.ndim == 3)
-    hipLaunchKernelGGL(encode_kernel<3>, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, ea);
-  else
-    hipLaunchKernelGGL(encode_kernel<2>, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, ea);
+  launch_encode((int)ndim, g_tune.encode_waves, xcd_grid(ea.nch), s, ea);
   ev_end(1, s);
   ev_begin(2, s);
-  if (!fa.fused) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, sa);
-  hipLaunchKernelGGL(finalize_kernel, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, fa);
+  if (!J.fin.fused) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, J.scan);
+  hipLaunchKernelGGL(finalize_kernel, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, J.fin);
   ev_end(2, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
 int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_elems,
                        void* d_ws, size_t ws_bytes, int32_t* d_status, void* stream) {
-  if (!d_in || !d_out || !d_ws || !d_status || out_cap_elems < 1) return TOPOSZP_E_INVALID_ARG;
-  if (((uintptr_t)d_in & 7) || ((uintptr_t)d_out & 3) || ((uintptr_t)d_ws & 255) || ((uintptr_t)d_status & 3))
-    return TOPOSZP_E_INVALID_ARG;
-  if (ws_bytes < kRegionOff + 4096) return TOPOSZP_E_CAPACITY;
+  DecJob J;
+  int slots = 0;
+  const int rc = build_dec(d_in, in_size, d_out, out_cap_elems, (uint8_t*)d_ws, ws_bytes, d_status, &J, &slots);
+  if (rc != TOPOSZP_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  uint64_t cap = out_cap_elems;
-  if (cap > (1ull << 31)) cap = (1ull << 31);
-  const uint64_t nch = ((cap + kB - 1) / kB + kB - 1) / kB;
-  DecArgs da;
-  da.in = d_in;
-  da.in_size = in_size;
-  da.out = d_out;
-  da.out_cap = out_cap_elems;
-  da.ws = (uint8_t*)d_ws;
-  da.ws_bytes = ws_bytes;
   for (int k = 3; k < 5; ++k) g_ev_used[k] = false;
   ev_begin(3, s);
-  hipLaunchKernelGGL(decode_kernel, dim3(xcd_grid((int)nch)), dim3(256), 0, s, da);
+  if (g_tune.decode_waves == 8)
+    hipLaunchKernelGGL(decode_kernel<8>, dim3(slots), dim3(512), 0, s, J.dec);
+  else
+    hipLaunchKernelGGL(decode_kernel<4>, dim3(slots), dim3(256), 0, s, J.dec);
   ev_end(3, s);
-  RefArgs ra;
-  ra.in = d_in;
-  ra.out = d_out;
-  ra.ws = (uint8_t*)d_ws;
-  ra.status = d_status;
   ev_begin(4, s);
-  hipLaunchKernelGGL(refine_kernel, dim3(xcd_grid((int)nch)), dim3(kRefThreads), 0, s, ra);
-  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, ra);
+  hipLaunchKernelGGL(refine_kernel, dim3(slots), dim3(kRefThreads), 0, s, J.ref);
+  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, J.ref);
   ev_end(4, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+size_t toposzp_compress_batch_workspace_size(uint32_t count, const toposzp_compress_job* h_jobs) {
+  if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs) return 0;
+  return comp_batch_layout(count, h_jobs, nullptr);
+}
+
+size_t toposzp_decompress_batch_workspace_size(uint32_t count, const toposzp_decompress_job* h_jobs) {
+  if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs) return 0;
+  return dec_batch_layout(count, h_jobs, nullptr);
+}
+
+int toposzp_compress_batch(uint32_t count, const toposzp_compress_job* h_jobs, const toposzp_params* params,
+                           void* d_ws, size_t ws_bytes, void* stream) {
+  if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs || !d_ws || ((uintptr_t)d_ws & 255))
+    return TOPOSZP_E_INVALID_ARG;
+  std::vector<size_t> offs(count);
+  const size_t need = comp_batch_layout(count, h_jobs, offs.data());
+  if (need == 0) return TOPOSZP_E_INVALID_ARG;
+  if (ws_bytes < need) return TOPOSZP_E_CAPACITY;
+  const size_t jo = tab_jobs_off((int)count);
+  std::vector<uint8_t> tab(jo + count * sizeof(CompJob));
+  BatchHdr* h = reinterpret_cast<BatchHdr*>(tab.data());
+  int* pre_r = reinterpret_cast<int*>(tab.data() + sizeof(BatchHdr));
+  int* pre_c = pre_r + count + 1;
+  CompJob* jobs = reinterpret_cast<CompJob*>(tab.data() + jo);
+  uint8_t* ws = (uint8_t*)d_ws;
+  long long nr = 0, nc = 0;
+  bool any_scan = false;
+  for (uint32_t i = 0; i < count; ++i) {
+    const toposzp_compress_job& q = h_jobs[i];
+    const size_t wsz = (i + 1 < count ? offs[i + 1] : need) - offs[i];
+    const int rc = build_comp(q.d_field, q.ndim, q.dims, q.eb_mode, q.eb, params, ws + offs[i], wsz, q.d_out,
+                              q.out_cap, q.d_out_size, q.d_status, &jobs[i]);
+    if (rc != TOPOSZP_OK) return rc;
+    pre_r[i] = (int)nr;
+    pre_c[i] = (int)nc;
+    nr += jobs[i].nrange;
+    nc += jobs[i].enc.nch;
+    any_scan |= !jobs[i].fin.fused;
+    if (nr > INT32_MAX / 2 || nc > INT32_MAX / 2) return TOPOSZP_E_UNSUPPORTED;
+  }
+  pre_r[count] = (int)nr;
+  pre_c[count] = (int)nc;
+  h->count = (int)count;
+  h->n_range = (int)nr;
+  h->n_chunk = (int)nc;
+  h->n_slot = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ws, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TOPOSZP_E_DEVICE;
+  const int wpc = g_tune.compress_wgs_per_cu;
+  if (nr > 0) hipLaunchKernelGGL(range_batch_kernel, dim3(batch_grid((int)nr, wpc)), dim3(256), 0, s, ws);
+  if (g_tune.encode_waves == 8)
+    hipLaunchKernelGGL(encode_batch_kernel<8>, dim3(batch_grid((int)nc, wpc)), dim3(512), 0, s, ws);
+  else
+    hipLaunchKernelGGL(encode_batch_kernel<4>, dim3(batch_grid((int)nc, wpc)), dim3(256), 0, s, ws);
+  if (any_scan) hipLaunchKernelGGL(scan_batch_kernel, dim3(batch_grid((int)count, 1)), dim3(1024), 0, s, ws);
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(batch_grid((int)nc, wpc)), dim3(256), 0, s, ws);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job* h_jobs, void* d_ws, size_t ws_bytes,
+                             void* stream) {
+  if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs || !d_ws || ((uintptr_t)d_ws & 255))
+    return TOPOSZP_E_INVALID_ARG;
+  std::vector<size_t> offs(count);
+  const size_t need = dec_batch_layout(count, h_jobs, offs.data());
+  if (need == 0) return TOPOSZP_E_INVALID_ARG;
+  if (ws_bytes < need) return TOPOSZP_E_CAPACITY;
+  const size_t jo = tab_jobs_off((int)count);
+  std::vector<uint8_t> tab(jo + count * sizeof(DecJob));
+  BatchHdr* h = reinterpret_cast<BatchHdr*>(tab.data());
+  int* pre = reinterpret_cast<int*>(tab.data() + sizeof(BatchHdr));
+  DecJob* jobs = reinterpret_cast<DecJob*>(tab.data() + jo);
+  uint8_t* ws = (uint8_t*)d_ws;
+  long long ns = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const toposzp_decompress_job& q = h_jobs[i];
+    const size_t wsz = (i + 1 < count ? offs[i + 1] : need) - offs[i];
+    int slots = 0;
+    const int rc = build_dec(q.d_in, q.in_size, q.d_out, q.out_cap_elems, ws + offs[i], wsz, q.d_status, &jobs[i],
+                             &slots);
+    if (rc != TOPOSZP_OK) return rc;
+    pre[i] = (int)ns;
+    ns += slots;
+    if (ns > INT32_MAX / 2) return TOPOSZP_E_UNSUPPORTED;
+  }
+  pre[count] = (int)ns;
+  h->count = (int)count;
+  h->n_range = (int)ns;
+  h->n_chunk = 0;
+  h->n_slot = (int)ns;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ws, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TOPOSZP_E_DEVICE;
+  const int wpc = g_tune.decompress_wgs_per_cu;
+  if (g_tune.decode_waves == 8)
+    hipLaunchKernelGGL(decode_batch_kernel<8>, dim3(batch_grid((int)ns, wpc)), dim3(512), 0, s, ws);
+  else
+    hipLaunchKernelGGL(decode_batch_kernel<4>, dim3(batch_grid((int)ns, wpc)), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(refine_batch_kernel, dim3(batch_grid((int)ns, 2 * wpc)), dim3(kRefThreads), 0, s, ws);
+  hipLaunchKernelGGL(tail_batch_kernel, dim3(batch_grid((int)count, 1)), dim3(1024), 0, s, ws);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job* h_jobs, const void* d_ws,
+                                   uint32_t index, int64_t out[5], void* stream) {
+  if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs || !d_ws || index >= count || !out)
+    return TOPOSZP_E_INVALID_ARG;
+  std::vector<size_t> offs(count);
+  if (dec_batch_layout(count, h_jobs, offs.data()) == 0) return TOPOSZP_E_INVALID_ARG;
+  return toposzp_decompress_stats((const uint8_t*)d_ws + offs[index], out, stream);
+}
+
+int toposzp_set_tuning(const toposzp_tuning* t) {
+  if (!t || !tuning_ok(*t)) return TOPOSZP_E_INVALID_ARG;
+  g_tune = *t;
+  return TOPOSZP_OK;
+}
+
+int toposzp_get_tuning(toposzp_tuning* t) {
+  if (!t) return TOPOSZP_E_INVALID_ARG;
+  *t = g_tune;
+  return TOPOSZP_OK;
+}
+
+int toposzp_autotune_compress_batch(uint32_t count, const toposzp_compress_job* h_jobs,
+                                    const toposzp_params* params, void* d_ws, size_t ws_bytes, void* stream,
+                                    toposzp_tuning* out) {
+  std::vector<toposzp_tuning> c;
+  for (int w : {4, 8})
+    for (int g : {2, 4, 8, 16}) c.push_back({w, g_tune.decode_waves, g, g_tune.decompress_wgs_per_cu});
+  return autotune(c, (hipStream_t)stream,
+                  [&]() { return toposzp_compress_batch(count, h_jobs, params, d_ws, ws_bytes, stream); }, out);
+}
+
+int toposzp_autotune_decompress_batch(uint32_t count, const toposzp_decompress_job* h_jobs, void* d_ws,
+                                      size_t ws_bytes, void* stream, toposzp_tuning* out) {
+  std::vector<toposzp_tuning> c;
+  for (int w : {4, 8})
+    for (int g : {2, 4, 8, 16}) c.push_back({g_tune.encode_waves, w, g_tune.compress_wgs_per_cu, g});
+  return autotune(c, (hipStream_t)stream,
+                  [&]() { return toposzp_decompress_batch(count, h_jobs, d_ws, ws_bytes, stream); }, out);
 }
 
 int toposzp_compress_sync(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode,

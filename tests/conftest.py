@@ -18,3 +18,13 @@ def ora():
     from oracle import oracle as o
     o.lib()
     return o
+
+
+@pytest.fixture(scope="session")
+def tsz():
+    """The GPU library's binding (GPU tests only)."""
+    import torch
+    import paper_2602_17552_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.lib()
+    return pkg

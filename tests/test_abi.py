@@ -45,7 +45,8 @@ def test_bound_matches_oracle_and_format(tsz, ora, shape):
     d[: len(shape)] = shape
     assert tsz.compress_bound(shape) == ora.lib().ora_compress_bound(len(shape), d, 0)
     n = int(np.prod(shape))
-    assert tsz.workspace_size(shape) >= 10 * n
+    # queue slot (4 B), replay state (1 B) and pending value (4 B) per point
+    assert tsz.workspace_size(shape) >= 9 * n
 
 
 def test_invalid_arguments_rejected_on_host(tsz):

@@ -16,15 +16,6 @@ SEG_NAMES = ["S1 const", "S2 widths", "S3 signs", "S4 first", "S6 labels", "R1",
              "X1", "X2", "S5 payload", "R5 rank payload"]
 
 
-@pytest.fixture(scope="module")
-def tsz():
-    import torch
-    import paper_2602_17552_amd as pkg
-    assert torch.cuda.is_available(), "GPU tests need a HIP device"
-    pkg.lib()
-    return pkg
-
-
 def _where(ora, s, k):
     if k < 512:
         return "header byte %d" % k
