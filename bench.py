@@ -87,6 +87,102 @@ def cpu_baseline(field, eb, target_s=10.0):
     }, s, rec
 
 
+def batch_leg(tsz, torch, dev, reps=20):
+    """The 64-field batch (48 2D + 16 3D, uneven sizes, bounds 1e-2..1e-4):
+    autotuned batched calls against one-field calls on the same fields."""
+    import numpy as np
+    from paper_2602_17552_amd import datagen
+    batch = datagen.batch_fields(48, 16, seed=3)
+    fields = [torch.from_numpy(f).to(dev) for f, _ in batch]
+    ebs = [eb for _, eb in batch]
+    nbytes = sum(f.numel() * 4 for f in fields)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    cb = tsz.CompressBatch(fields, ebs)
+    tune_c = cb.autotune()
+    torch.cuda.synchronize()
+    ms_cb = timed(cb.run, reps)
+    st, streams = cb.results()
+    assert st == [0] * len(fields)
+    streams = [x.clone() for x in streams]
+    S = sum(x.numel() for x in streams)
+    db = tsz.DecompressBatch(streams, [tuple(f.shape) for f in fields])
+    tune_d = db.autotune()
+    torch.cuda.synchronize()
+    ms_db = timed(db.run, reps)
+    assert db.status.cpu().tolist() == [0] * len(fields)
+
+    # the one-field form on the same fields (each with its own workspace)
+    wss = [tsz.Workspace(tuple(f.shape), dev) for f in fields]
+    outs = [torch.empty(tsz.compress_bound(tuple(f.shape)), dtype=torch.uint8, device=dev) for f in fields]
+    sizes = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in fields]
+    stt = torch.zeros(1, dtype=torch.int32, device=dev)
+    recs = [torch.empty(tuple(f.shape), dtype=torch.float32, device=dev) for f in fields]
+
+    def one_c():
+        for i, f in enumerate(fields):
+            tsz.compress_async(f, ebs[i], "rel", ws=wss[i], out=outs[i], size=sizes[i], status=stt)
+
+    def one_d():
+        for i in range(len(fields)):
+            tsz.decompress_async(streams[i], streams[i].numel(), recs[i], ws=wss[i], status=stt)
+
+    ms_1c = timed(one_c, max(3, reps // 4))
+    ms_1d = timed(one_d, max(3, reps // 4))
+    same = all(torch.equal(outs[i][: streams[i].numel()], streams[i]) for i in range(len(fields))) and \
+        all(torch.equal(recs[i].view(torch.int32), db.recs[i].view(torch.int32)) for i in range(len(fields)))
+    alg_c = 4 * sum(f.numel() for f in fields) + S
+    gb = lambda ms: round(nbytes / (ms * 1e-3) / 1e9, 2)
+    return {"workload": "64 fields (48 2D sides log-uniform 128-2048, 16 3D sides 32-192), rel bounds "
+                        "from {1e-2,1e-3,1e-4}, seed 3",
+            "field_bytes": nbytes, "stream_bytes": S,
+            "batched": {"compress_gbps": gb(ms_cb), "decompress_gbps": gb(ms_db),
+                        "compress_ms": round(ms_cb, 4), "decompress_ms": round(ms_db, 4),
+                        "compress_hbm_frac": round(alg_c / (ms_cb * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "decompress_hbm_frac": round(alg_c / (ms_db * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "tuning": {"compress": tune_c, "decompress": tune_d}},
+            "one_field_calls": {"compress_gbps": gb(ms_1c), "decompress_gbps": gb(ms_1d),
+                                "compress_ms": round(ms_1c, 4), "decompress_ms": round(ms_1d, 4)},
+            "batched_equals_one_field": bool(same)}, fields, ebs, streams
+
+
+def serve_leg(tsz, torch, fields, ebs, streams, seconds):
+    """Poisson arrivals (200 req/s, 70/30 compress/decompress) of requests on
+    the batch's fields and streams, served with continuous batching under a
+    64 GB admission limit."""
+    import numpy as np
+    from paper_2602_17552_amd import datagen, serve
+    trace = datagen.serve_trace(rate=200.0, duration=seconds, frac_compress=0.7, seed=4)
+    rng = np.random.default_rng(8)
+
+    def make(i, t, op):
+        k = int(rng.integers(0, len(fields)))
+        src = fields[k] if op == "compress" else streams[k]
+        return serve.Request(i, op, t, src=src, shape=tuple(fields[k].shape), eb=ebs[k],
+                             nbytes=fields[k].numel() * 4, tag=k)
+
+    srv = serve.Server(mem_limit=64 << 30, max_batch=64, streams=4, keep_results=False)
+    reqs = serve.run_trace(srv, trace, make, realtime=True, deadline=seconds + 120.0)
+    st = srv.stats()
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    st.update({"trace": "Poisson 200 req/s, %g s, 70/30 compress/decompress, fields of the batch" % seconds,
+               "sustained_gbps": round(sum(r.nbytes for r in reqs) / span / 1e9, 4),
+               "offered_gbps": round(sum(r.nbytes for r in reqs) / seconds / 1e9, 4),
+               "admission_limit_bytes": 64 << 30})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +192,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--probe", action="store_true",
                     help="a few steps only (for profiler runs), no JSON line")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the served-form trace (0 skips it; 60 is the full configuration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -239,6 +338,13 @@ def main():
                              "ratio": round(nbytes / n2, 3), "status_ok": ok2,
                              "missed_cps": {"FN": ev2["FN"], "FP": ev2["FP"], "FT": ev2["FT"]}}
 
+    batched = served = None
+    if not args.no_batch:
+        batched, bf, be, bs = batch_leg(tsz, torch, dev)
+        if args.serve_seconds > 0:
+            served = serve_leg(tsz, torch, bf, be, bs, args.serve_seconds)
+        del bf, bs
+
     S = slen[0]
     # algorithmic bytes per launch: encode reads the field and writes the
     # stream; decode reads the stream and writes the field
@@ -291,6 +397,8 @@ def main():
         "roofline": roofline,
         "valu": valu,
         "other_bounds": other,
+        "batched_form": batched,
+        "served_form": served,
         "cpu_baseline": cpu,
         "parity_with_oracle": parity,
         "wall_s_timed_loop": round(t_wall, 3),
