@@ -143,6 +143,15 @@ int toposzp_decompress_sync(const uint8_t *d_in, size_t in_size, float *d_out,
                             size_t out_cap_elems, void *d_ws, size_t ws_bytes,
                             void *stream);
 
+/* Topological errors of a reconstruction against its original (Section
+ * III-B), computed on the device with the library's classifier.  d_orig and
+ * d_recon: N float32 values each (dims as for compression).  d_counts
+ * (int64[11], device) receives FN, FP, FT, then the original's points by class
+ * r, m, s, M, then FN by original class r, m, s, M; d_max_err (double,
+ * device) the largest |orig - recon|.  Both are overwritten. */
+int toposzp_eval(const float *d_orig, const float *d_recon, uint32_t ndim, const uint64_t *dims,
+                 int64_t *d_counts, double *d_max_err, void *stream);
+
 /* ---- Batched form: many fields of uneven sizes per call (one launch per
  * stage for the whole batch; every field's stream and reconstruction are
  * those of a one-field call).  Job arrays are host arrays of `count`

@@ -24,7 +24,7 @@ SYMBOLS = [
     "toposzp_compress_batch_workspace_size", "toposzp_decompress_batch_workspace_size",
     "toposzp_compress_batch", "toposzp_decompress_batch", "toposzp_decompress_batch_stats",
     "toposzp_set_tuning", "toposzp_get_tuning", "toposzp_autotune_compress_batch",
-    "toposzp_autotune_decompress_batch",
+    "toposzp_autotune_decompress_batch", "toposzp_eval",
 ]
 
 
@@ -103,6 +103,8 @@ def lib():
         L.toposzp_set_timing.argtypes = [C.c_int]
         L.toposzp_kernel_times.restype = C.c_int
         L.toposzp_kernel_times.argtypes = [C.POINTER(C.c_float), C.c_int]
+        L.toposzp_eval.restype = C.c_int
+        L.toposzp_eval.argtypes = [vp, vp, C.c_uint32, u64p, vp, vp, vp]
         cjp, djp = C.POINTER(CompressJob), C.POINTER(DecompressJob)
         L.toposzp_compress_batch_workspace_size.restype = C.c_size_t
         L.toposzp_compress_batch_workspace_size.argtypes = [C.c_uint32, cjp]
@@ -260,6 +262,25 @@ def inspect(header: bytes):
     d = {k: getattr(info, k) for k, _ in Info._fields_}
     d["dims"] = [int(x) for x in info.dims]
     return rc, d
+
+
+def eval_topology(orig, recon, stream=None):
+    """False negatives / positives / types of `recon` against `orig` (Section
+    III-B) on the GPU: dict with FN, FP, FT, critical points of the original
+    by class, FN by class, and the largest absolute error."""
+    import torch
+    if orig.shape != recon.shape or orig.dtype != torch.float32 or recon.dtype != torch.float32:
+        raise TypeError("orig and recon must be float32 tensors of one shape")
+    counts = torch.zeros(11, dtype=torch.int64, device=orig.device)
+    mx = torch.zeros(1, dtype=torch.float64, device=orig.device)
+    shape = tuple(orig.shape)
+    rc = lib().toposzp_eval(C.c_void_p(orig.data_ptr()), C.c_void_p(recon.data_ptr()), len(shape), _dims(shape),
+                            C.c_void_p(counts.data_ptr()), C.c_void_p(mx.data_ptr()), _stream(stream))
+    if rc != OK:
+        raise RuntimeError(f"toposzp_eval: {strerror(rc)} ({rc})")
+    c = counts.cpu().tolist()
+    return {"FN": c[0], "FP": c[1], "FT": c[2], "cp_r": c[3], "cp_min": c[4], "cp_sad": c[5], "cp_max": c[6],
+            "FN_r": c[7], "FN_min": c[8], "FN_sad": c[9], "FN_max": c[10], "max_err": float(mx.item())}
 
 
 def set_timing(enable: bool):

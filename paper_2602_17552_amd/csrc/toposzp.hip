@@ -2119,6 +2119,69 @@ __device__ __forceinline__ void tail_body(const RefArgs& a) {
 __global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) { tail_body(a); }
 
 // ---------------------------------------------------------------------------
+// Topological errors of a reconstruction (Section III-B): per point, the
+// class in the original and in the reconstruction; false negatives (a
+// critical point that became regular), false positives (a regular point
+// that became critical) and false types (critical in both, of another type),
+// with the largest absolute difference.
+
+__global__ void eval_clear_kernel(unsigned long long* counts, double* max_err) {
+  if (threadIdx.x < 11) counts[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *max_err = 0.0;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void eval_kernel(const float* __restrict__ o, const float* __restrict__ r,
+                                                   GeomD g, unsigned long long* counts, double* max_err) {
+  __shared__ unsigned s_c[11];
+  __shared__ unsigned long long s_m;
+  const int tid = threadIdx.x;
+  if (tid < 11) s_c[tid] = 0;
+  if (tid == 0) s_m = 0;
+  __syncthreads();
+  const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
+  unsigned c[11] = {0};
+  double mx = 0.0;
+  for (int i = blockIdx.x * 256 + tid; i < g.n; i += gridDim.x * 256) {
+    const Pt pc = coords_of(i, g);
+    unsigned avm = (pc.x > 0 ? 1u : 0u) | (pc.x < g.nx - 1 ? 2u : 0u) | (pc.y > 0 ? 4u : 0u) |
+                   (pc.y < g.ny - 1 ? 8u : 0u);
+    if (ND == 3) avm |= (pc.z > 0 ? 16u : 0u) | (pc.z < g.nz - 1 ? 32u : 0u);
+    const int nbi[6] = {i - 1, i + 1, i - g.nx, i + g.nx, i - g.nxy, i + g.nxy};
+    float no[6], nr[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int q = ((avm >> j) & 1u) ? nbi[j] : i;
+      no[j] = o[q];
+      nr[j] = r[q];
+    }
+    const int lo = classify_bits(o[i], no, avm, ndeg), lr = classify_bits(r[i], nr, avm, ndeg);
+    c[3 + lo]++;
+    if (lo != CLS_R && lr == CLS_R) {
+      c[0]++;
+      c[7 + lo]++;
+    }
+    if (lo == CLS_R && lr != CLS_R) c[1]++;
+    if (lo != CLS_R && lr != CLS_R && lo != lr) c[2]++;
+    mx = fmax(mx, fabs((double)o[i] - (double)r[i]));
+  }
+#pragma unroll
+  for (int k = 0; k < 11; ++k) {
+    unsigned v = c[k];
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v += (unsigned)__shfl_xor((int)v, s);
+    if ((tid & 63) == 0 && v) atomicAdd(&s_c[k], v);
+  }
+  unsigned long long mb = (unsigned long long)__double_as_longlong(mx);  // non-negative: ordered as integers
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) mb = max(mb, (unsigned long long)__shfl_xor((long long)mb, s));
+  if ((tid & 63) == 0) atomicMax(&s_m, mb);
+  __syncthreads();
+  if (tid < 11 && s_c[tid]) atomicAdd(&counts[tid], (unsigned long long)s_c[tid]);
+  if (tid == 0) atomicMax(reinterpret_cast<unsigned long long*>(max_err), s_m);
+}
+
+// ---------------------------------------------------------------------------
 // Batched form: many fields (or streams) in one launch per stage.  A table
 // of per-field kernel arguments sits at the head of the workspace; a
 // persistent grid walks the (field, chunk) items, each XCD taking a
@@ -2612,6 +2675,33 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   hipLaunchKernelGGL(refine_kernel, dim3(slots), dim3(kRefThreads), 0, s, J.ref);
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, J.ref);
   ev_end(4, s);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_eval(const float* d_orig, const float* d_recon, uint32_t ndim, const uint64_t* dims,
+                 int64_t* d_counts, double* d_max_err, void* stream) {
+  HostGeom hg;
+  const int rc = host_geom(ndim, dims, &hg);
+  if (rc != TOPOSZP_OK) return rc;
+  if (!d_orig || !d_recon || !d_counts || !d_max_err || ((uintptr_t)d_orig & 3) || ((uintptr_t)d_recon & 3) ||
+      ((uintptr_t)d_counts & 7) || ((uintptr_t)d_max_err & 7))
+    return TOPOSZP_E_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  GeomD g;
+  g.n = hg.g.n;
+  g.nx = hg.g.nx;
+  g.ny = hg.g.ny;
+  g.nz = hg.g.nz;
+  g.nxy = hg.g.nx * hg.g.ny;
+  g.dx = make_div((unsigned)g.nx);
+  g.dy = make_div((unsigned)g.ny);
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(d_counts);
+  hipLaunchKernelGGL(eval_clear_kernel, dim3(1), dim3(64), 0, s, cnt, d_max_err);
+  const unsigned grid = (unsigned)std::min<long long>(((long long)g.n + 255) / 256, 4096);
+  if (ndim == 3)
+    hipLaunchKernelGGL(eval_kernel<3>, dim3(grid), dim3(256), 0, s, d_orig, d_recon, g, cnt, d_max_err);
+  else
+    hipLaunchKernelGGL(eval_kernel<2>, dim3(grid), dim3(256), 0, s, d_orig, d_recon, g, cnt, d_max_err);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 

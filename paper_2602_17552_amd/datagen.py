@@ -20,6 +20,8 @@ __all__ = [
     "noise",
     "checker_2d",
     "checker_3d",
+    "climate_stand_in",
+    "CLIMATE_SHAPES",
     "cfg0",
     "cfg1",
     "cfg2",
@@ -129,6 +131,22 @@ def checker_3d(n0: int, n1: int, n2: int, seed: int = 0, noise_sd: float = 0.2) 
     z, y, x = np.mgrid[0:n0, 0:n1, 0:n2].astype(np.float64)
     f = (-1.0) ** x - 0.6 * (-1.0) ** y + 0.3 * (-1.0) ** z + noise_sd * rng.standard_normal((n0, n1, n2))
     return f.astype(np.float32)
+
+
+# Grid shapes of the five CESM datasets of the paper's evaluation
+# (Section V-A, datasets table).
+CLIMATE_SHAPES = {"ATM": (1800, 3600), "CLIMATE": (768, 1152), "ICE": (384, 320),
+                  "LAND": (192, 288), "OCEAN": (384, 320)}
+
+
+def climate_stand_in(name: str, seed: int = 0) -> np.ndarray:
+    """A field shaped like one of the paper's CESM datasets: 64 plane waves
+    (amplitude |k|^-1.5) plus N(0, 1e-2^2) noise, min-max normalised to
+    [0, 1] so that absolute bounds of 1e-3..1e-5 are relative to the range."""
+    ny, nx = CLIMATE_SHAPES[name]
+    f = sinusoids_2d(ny, nx, 64, seed=1000 + 17 * seed + len(name), noise_sd=1e-2).astype(np.float64)
+    lo, hi = float(f.min()), float(f.max())
+    return ((f - lo) / (hi - lo)).astype(np.float32)
 
 
 def cfg0() -> np.ndarray:
