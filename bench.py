@@ -338,6 +338,28 @@ def main():
                              "ratio": round(nbytes / n2, 3), "status_ok": ok2,
                              "missed_cps": {"FN": ev2["FN"], "FP": ev2["FP"], "FT": ev2["FT"]}}
 
+    # field-scope ranks (the paper's whole-field reading of the rank set) on
+    # the same field: a sort of the flattened extrema joins the path
+    wsf = tsz.Workspace(SHAPE, dev, rank_scope=1)
+    capf = tsz.compress_bound(SHAPE, 1)
+    outf = torch.empty(capf, dtype=torch.uint8, device=dev)
+    szf = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def compf(k):
+        tsz.compress_async(ins[k], EB, "rel", ws=wsf, out=outf, size=szf, status=cst, rank_scope=1)
+    ms_cf = timed(compf, max(10, args.steps // 2), 3)
+    assert int(cst.item()) == 0
+    nf = int(szf.item())
+
+    def decf(k):
+        tsz.decompress_async(outf, nf, recs[k], ws=wsf, status=dst)
+    ms_df = timed(decf, max(10, args.steps // 2), 3)
+    assert int(dst.item()) == 0
+    field_scope = {"compress_gbps": round(nbytes / (ms_cf * 1e-3) / 1e9, 2),
+                   "decompress_gbps": round(nbytes / (ms_df * 1e-3) / 1e9, 2),
+                   "ratio": round(nbytes / nf, 3)}
+    del wsf, outf
+
     batched = served = None
     if not args.no_batch:
         batched, bf, be, bs = batch_leg(tsz, torch, dev)
@@ -397,6 +419,7 @@ def main():
         "roofline": roofline,
         "valu": valu,
         "other_bounds": other,
+        "field_scope_ranks": field_scope,
         "batched_form": batched,
         "served_form": served,
         "cpu_baseline": cpu,

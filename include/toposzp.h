@@ -58,8 +58,8 @@ extern "C" {
 typedef struct {
   uint32_t block;     /* points per block; must be 64 (default 64) */
   int32_t rank_scope; /* 0 = ranks among flattened extrema of the same 64-point
-                         block (default); 1 = whole field, which this build
-                         cannot compress (TOPOSZP_E_UNSUPPORTED) but decodes */
+                         block (default); 1 = whole field (needs the _ex sizes;
+                         not in the batched form: TOPOSZP_E_UNSUPPORTED there) */
   int32_t rbf_policy; /* 0 = adaptive kernel size/width (default),
                          1 = always k_size 3 */
   int32_t max_rounds; /* cap on saddle-refinement rounds, 1..65535 (16) */
@@ -91,6 +91,12 @@ size_t toposzp_compress_bound(uint32_t ndim, const uint64_t *dims);
 /* Device workspace bytes that compression and decompression of a field of
  * these dims need (one size serves both).  0 if the dims are invalid. */
 size_t toposzp_workspace_size(uint32_t ndim, const uint64_t *dims);
+
+/* The same two sizes for a rank scope (params.rank_scope: 0 block, 1 field).
+ * Field-scope ranks reach 31 bits, and their compression sorts the
+ * flattened extrema of the whole field, so both sizes are larger. */
+size_t toposzp_compress_bound_ex(uint32_t ndim, const uint64_t *dims, int32_t rank_scope);
+size_t toposzp_workspace_size_ex(uint32_t ndim, const uint64_t *dims, int32_t rank_scope);
 
 /* Clears a freshly allocated workspace (enqueued on `stream`).  Must be called
  * once before a workspace's first use and again after any call on it that

@@ -24,7 +24,8 @@ SYMBOLS = [
     "toposzp_compress_batch_workspace_size", "toposzp_decompress_batch_workspace_size",
     "toposzp_compress_batch", "toposzp_decompress_batch", "toposzp_decompress_batch_stats",
     "toposzp_set_tuning", "toposzp_get_tuning", "toposzp_autotune_compress_batch",
-    "toposzp_autotune_decompress_batch", "toposzp_eval",
+    "toposzp_autotune_decompress_batch", "toposzp_eval", "toposzp_compress_bound_ex",
+    "toposzp_workspace_size_ex",
 ]
 
 
@@ -103,6 +104,10 @@ def lib():
         L.toposzp_set_timing.argtypes = [C.c_int]
         L.toposzp_kernel_times.restype = C.c_int
         L.toposzp_kernel_times.argtypes = [C.POINTER(C.c_float), C.c_int]
+        L.toposzp_compress_bound_ex.restype = C.c_size_t
+        L.toposzp_compress_bound_ex.argtypes = [C.c_uint32, u64p, C.c_int32]
+        L.toposzp_workspace_size_ex.restype = C.c_size_t
+        L.toposzp_workspace_size_ex.argtypes = [C.c_uint32, u64p, C.c_int32]
         L.toposzp_eval.restype = C.c_int
         L.toposzp_eval.argtypes = [vp, vp, C.c_uint32, u64p, vp, vp, vp]
         cjp, djp = C.POINTER(CompressJob), C.POINTER(DecompressJob)
@@ -148,21 +153,21 @@ def strerror(status: int) -> str:
     return lib().toposzp_strerror(int(status)).decode()
 
 
-def compress_bound(shape) -> int:
-    return int(lib().toposzp_compress_bound(len(shape), _dims(shape)))
+def compress_bound(shape, rank_scope: int = 0) -> int:
+    return int(lib().toposzp_compress_bound_ex(len(shape), _dims(shape), int(rank_scope)))
 
 
-def workspace_size(shape) -> int:
-    return int(lib().toposzp_workspace_size(len(shape), _dims(shape)))
+def workspace_size(shape, rank_scope: int = 0) -> int:
+    return int(lib().toposzp_workspace_size_ex(len(shape), _dims(shape), int(rank_scope)))
 
 
 class Workspace:
     """Device workspace sized for fields up to `shape` (compress and
     decompress), cleared once on creation."""
 
-    def __init__(self, shape, device="cuda", stream=None):
+    def __init__(self, shape, device="cuda", stream=None, rank_scope: int = 0):
         import torch
-        nbytes = workspace_size(shape)
+        nbytes = workspace_size(shape, rank_scope)
         if nbytes == 0:
             raise ValueError(f"invalid field shape {shape}")
         self.shape = tuple(shape)
@@ -190,9 +195,10 @@ def compress_async(field, eb, mode="rel", ws=None, out=None, size=None, status=N
     if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
         raise TypeError("field must be a contiguous float32 CUDA tensor")
     shape = tuple(field.shape)
-    ws = ws or Workspace(shape, field.device, stream)
+    scope = int(params.get("rank_scope", 0)) if params.get("topo", True) else 0
+    ws = ws or Workspace(shape, field.device, stream, scope)
     if out is None:
-        out = torch.empty(compress_bound(shape), dtype=torch.uint8, device=field.device)
+        out = torch.empty(compress_bound(shape, scope), dtype=torch.uint8, device=field.device)
     if size is None:
         size = torch.zeros(1, dtype=torch.int64, device=field.device)
     if status is None:

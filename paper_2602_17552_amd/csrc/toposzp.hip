@@ -41,6 +41,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "toposzp.h"
 
 // The compiler's lane-write intrinsic (v_writelane_b32): lane `l` (uniform)
@@ -115,14 +117,17 @@ __host__ __device__ constexpr uint64_t al256(uint64_t x) { return (x + 255) & ~u
 struct CompLayout {
   uint64_t tot_d, tot_r, cflag, stage_d, stage_r, end;
 };
-__host__ __device__ inline CompLayout comp_layout(uint64_t nch) {
+// Rank planes per block the staging holds: 7 for block-scope ranks (at most
+// 64), 31 for field-scope ranks.
+__host__ __device__ constexpr int rank_w(int field) { return field ? kMaxWRankAny : kMaxWRankBlk; }
+__host__ __device__ inline CompLayout comp_layout(uint64_t nch, int field = 0) {
   CompLayout L;
   L.tot_d = kRegionOff;
   L.tot_r = L.tot_d + 4 * nch;
   L.cflag = L.tot_r + 4 * nch;
   L.stage_d = al256(L.cflag + 4 * nch);
   L.stage_r = al256(L.stage_d + 8ull * kB * kMaxWData * nch);
-  L.end = al256(L.stage_r + 8ull * kB * kMaxWRankBlk * nch);
+  L.end = al256(L.stage_r + 8ull * kB * rank_w(field) * nch);
   return L;
 }
 
@@ -344,15 +349,18 @@ struct EncArgs {
   uint8_t* out;
   uint8_t* ws;
   GeomD gd;
-  int nb, nch, topo, eb_mode, nrange;
+  int nb, nch, topo, eb_mode, nrange, field;
   double eb;
   float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
+  unsigned long long* keys;  // field scope: sort keys of the mark pass
+  unsigned* vals;            // and their point indices
+  const int* delta;          // field scope: ranks per point for the encode pass
 };
 
 struct ScanArgs {
   uint8_t* ws;
-  int nch, eb_mode, nrange;
+  int nch, eb_mode, nrange, field;
   double eb;
   float e_abs;
 };
@@ -364,7 +372,7 @@ struct FinArgs {
   int32_t* status;
   Geom g;
   uint64_t dims[3];
-  int nb, nch, topo, eb_mode, rbf_policy, max_rounds, nrange, fused;
+  int nb, nch, topo, eb_mode, rbf_policy, max_rounds, nrange, fused, field;
   double eb;
   float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
@@ -558,10 +566,12 @@ __device__ __forceinline__ EncIn enc_fetch(const float* __restrict__ f, int b, i
   return r;
 }
 
-// LDS of the encode kernel (one per workgroup, whatever the dimension).
-struct EncShared {
-  unsigned pd[kB][2 * kMaxWData];     // a block's data planes, 2 words each
-  unsigned pr[kB][2 * kMaxWRankBlk];  // its rank planes
+// LDS of the encode kernel (one per workgroup, whatever the dimension);
+// MAXWR = widest rank planes (block or field scope).
+template <int MAXWR>
+struct EncSharedT {
+  unsigned pd[kB][2 * kMaxWData];  // a block's data planes, 2 words each
+  unsigned pr[kB][2 * MAXWR];      // its rank planes
   unsigned long long sign[kB], rsign[kB];
   int first[kB], rfirst[kB];
   unsigned lab[kB * 4];
@@ -571,10 +581,19 @@ struct EncShared {
   unsigned flags;
 };
 
+using EncShared = EncSharedT<kMaxWRankBlk>;
+using EncSharedField = EncSharedT<kMaxWRankAny>;
+
+// Encode modes: ranks within the block; the field-scope mark pass (sort keys
+// of the flattened extrema, nothing encoded); encoding with field-scope ranks.
+enum { kModeBlock = 0, kModeMark = 1, kModeField = 2 };
+
 // Encodes chunk c of the field of `a` (all WAVES waves of the workgroup).
-template <int ND, int WAVES>
-__device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& sh) {
+template <int ND, int WAVES, int MODE = kModeBlock>
+__device__ __forceinline__ void encode_body(const EncArgs& a, int c,
+                                            EncSharedT<MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk>& sh) {
   constexpr int BPW = kB / WAVES;  // blocks per wave
+  constexpr int MAXWR = MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk;
   static_assert(BPW % 4 == 0, "four blocks in flight per wave");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -682,7 +701,25 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
     // class and bin in this block: 1 + number less extreme; a flattened
     // saddle gets 1
     int delta = 0;
-    if (topo) {
+    if (MODE == kModeMark) {
+      // sort key of each flattened extremum: class, bin, then the order in
+      // which less extreme values come first; every other point sorts last
+      const unsigned long long ext = lostm & (m_min | m_max);
+      const bool ismax = lane_in(m_max);
+      const unsigned ord = (unsigned)(ismax ? fkey(av) : -fkey(av)) ^ 0x80000000u;
+      const unsigned long long key = ((unsigned long long)(ismax ? 1u : 0u) << 55) |
+                                     ((unsigned long long)(unsigned)(q + (1 << 22)) << 32) | ord;
+      if (i < n) {
+        a.keys[i] = lane_in(ext) ? key : ~0ull;
+        a.vals[i] = (unsigned)i;
+      }
+      return;
+    }
+    if (MODE == kModeField && topo) {
+      // field-scope ranks come from the sorted pass; a flattened saddle gets 1
+      const unsigned long long ext = lostm & (m_min | m_max);
+      delta = lane_in(ext) ? a.delta[i] : (lane_in(lostm) ? 1 : 0);
+    } else if (topo) {
       const unsigned long long ext = lostm & (m_min | m_max);
       int cnt = 0;
       if (ext) {
@@ -730,7 +767,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
       unsigned long long rsign;
       int rfirst;
       bool rover = false;
-      const int wr = encode_block<kMaxWRankBlk, 3>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
+      const int wr = encode_block<MAXWR, MAXWR == kMaxWRankBlk ? 3 : 5>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
       if (lane == 0) {
         sh.wr[lb] = wr;
         sh.rsign[lb] = rsign;
@@ -754,6 +791,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
     block(P3, bw + k + 3);
     P3 = enc_fetch<ND>(f, min(bw + k + 7, blast), lane, g);
   }
+  if (MODE == kModeMark) return;  // the keys are written; the encode pass reports errors
   {
     const bool nf = nfm != 0, qo = qom != 0 || wover;
     if (lane == 0 && (nf || qo)) atomicOr(&sh.flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
@@ -783,7 +821,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
   }
 
   // chunk: constant-block bitmaps, local prefix of widths, chunk totals
-  const CompLayout L = comp_layout((uint64_t)a.nch);
+  const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
   if (wv == 0) {
     const int b = c * kB + lane;
     const bool bv = b < a.nb;
@@ -820,7 +858,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
     }
     if (topo) {
       const int totr = 2 * sh.pfr[kB];
-      unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * kMaxWRankBlk;
+      unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * MAXWR;
       for (int o = tid; o < totr; o += WAVES * 64) {
         int lo = 0, hi = kB;
         while (hi - lo > 1) {
@@ -839,11 +877,37 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c, EncShared& 
   }
 }
 
-template <int ND, int WAVES>
+template <int ND, int WAVES, int MODE = kModeBlock>
 __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
-  __shared__ EncShared sh;
+  __shared__ EncSharedT<MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk> sh;
   const int c = xcd_chunk(blockIdx.x, a.nch);
-  if (c < a.nch) encode_body<ND, WAVES>(a, c, sh);
+  if (c < a.nch) encode_body<ND, WAVES, MODE>(a, c, sh);
+}
+
+// Field-scope ranks from the sorted keys: a flattened extremum's rank is 1 +
+// the number of entries of its (class, bin) group sorted before its value
+// (ties share a rank).  Both starts are lower bounds in the sorted prefix.
+__global__ __launch_bounds__(256) void fs_rank_kernel(const unsigned long long* __restrict__ keys,
+                                                      const unsigned* __restrict__ vals, int n, int* delta) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const unsigned long long k = keys[i];
+    if (k == ~0ull) continue;  // not a flattened extremum
+    const unsigned long long gk = k & ~0xFFFFFFFFull;
+    int lo = 0, hi = i;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (keys[mid] < gk) lo = mid + 1;
+      else hi = mid;
+    }
+    const int g0 = lo;
+    hi = i;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (keys[mid] < k) lo = mid + 1;
+      else hi = mid;
+    }
+    delta[vals[i]] = 1 + lo - g0;
+  }
 }
 
 // Exclusive scan of the chunk plane totals (in place), flags, and the bound.
@@ -852,7 +916,7 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
   __shared__ unsigned long long s_carry[2];
   __shared__ unsigned s_fl;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const CompLayout L = comp_layout((uint64_t)a.nch);
+  const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
   unsigned* td = reinterpret_cast<unsigned*>(a.ws + L.tot_d);
   unsigned* tr = reinterpret_cast<unsigned*>(a.ws + L.tot_r);
   const unsigned* cf = reinterpret_cast<const unsigned*>(a.ws + L.cflag);
@@ -942,7 +1006,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool last = c == a.nch - 1;  // writes the header
-  const CompLayout L = comp_layout((uint64_t)a.nch);
+  const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
   const unsigned* td = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
   const unsigned* tr = reinterpret_cast<const unsigned*>(a.ws + L.tot_r);
   const unsigned* cf = reinterpret_cast<const unsigned*>(a.ws + L.cflag);
@@ -1029,7 +1093,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * b0;
     if (a.topo) {
       const uint64_t* rsrc =
-          reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * kMaxWRankBlk;
+          reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * rank_w(a.field);
       uint64_t* rdst = reinterpret_cast<uint64_t*>(a.out + a.off[S5] + 8 * totd) + r0;
       for (uint64_t o = tid; o < nr; o += blockDim.x) rdst[o] = rsrc[o];
       if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * r0;
@@ -1055,7 +1119,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     hdr[0] = 'T'; hdr[1] = 'S'; hdr[2] = 'Z'; hdr[3] = '1';
     put2(hdr, 4, 1);
     hdr[6] = (uint8_t)a.g.ndim;
-    hdr[7] = (uint8_t)(a.topo ? 1 : 0);
+    hdr[7] = (uint8_t)((a.topo ? 1 : 0) | (a.field ? 2 : 0));
     for (int d = 0; d < 3; ++d) put8(hdr, 8 + 8 * d, a.dims[d]);
     put8(hdr, 32, (uint64_t)a.g.n);
     put8(hdr, 40, (uint64_t)a.nb);
@@ -1139,7 +1203,7 @@ __device__ __forceinline__ T rd(const uint8_t* p, int off) {
 // Header checks (one wave): the header is copied to LDS in parallel, then
 // lane 0 checks the checksum, field ranges and the segment table against the
 // layout rule.  Result in *h: ok = 0 corrupt, -1 capacity, 1 good.
-__device__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_cap, Hdr* h,
+__device__ __forceinline__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_cap, Hdr* h,
                              uint8_t* hb, int lane) {
   const bool good = in_size >= (uint64_t)kHdr;
   unsigned sa = 0, sb = 0;
@@ -2371,6 +2435,33 @@ void ev_end(int k, hipStream_t s) {
   g_ev_used[k] = true;
 }
 
+// Field-scope compression: sort keys and indices (in and out), ranks per
+// point and the sort's temporary storage, after the compression region.
+struct FieldLayout {
+  uint64_t keys_in, vals_in, keys_out, vals_out, delta, tmp, end;
+  size_t tmp_bytes;
+};
+FieldLayout field_layout(const HostGeom& hg) {
+  FieldLayout F;
+  const uint64_t n = (uint64_t)hg.g.n;
+  F.tmp_bytes = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, F.tmp_bytes, (const unsigned long long*)nullptr,
+                                  (unsigned long long*)nullptr, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                  (unsigned)n, 0, 56, (hipStream_t)0);
+  F.keys_in = al256(comp_layout(hg.nch, 1).end);
+  F.vals_in = al256(F.keys_in + 8 * n);
+  F.keys_out = al256(F.vals_in + 4 * n);
+  F.vals_out = al256(F.keys_out + 8 * n);
+  F.delta = al256(F.vals_out + 4 * n);
+  F.tmp = al256(F.delta + 4 * n);
+  F.end = al256(F.tmp + F.tmp_bytes);
+  return F;
+}
+size_t ws_need_field(const HostGeom& hg) {
+  const uint64_t c = field_layout(hg).end, d = dec_layout(hg.nb, hg.nch).end;
+  return (size_t)(c > d ? c : d);
+}
+
 size_t ws_need_n(uint64_t n) {
   const uint64_t nb = (n + kB - 1) / kB, nch = (nb + kB - 1) / kB;
   const uint64_t c = comp_layout(nch).end, d = dec_layout(nb, nch).end;
@@ -2411,7 +2502,7 @@ unsigned batch_grid(int items, int wgs_per_cu) {
 // Checks one compression request and fills its kernel arguments.
 int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode, double eb,
                const toposzp_params* params, uint8_t* d_ws, size_t ws_bytes, uint8_t* d_out, size_t out_cap,
-               uint64_t* d_out_size, int32_t* d_status, CompJob* J) {
+               uint64_t* d_out_size, int32_t* d_status, CompJob* J, bool allow_field = true) {
   toposzp_params p = {64, 0, 0, 16, 1};
   if (params) p = *params;
   HostGeom hg;
@@ -2426,9 +2517,10 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   if (p.block != (uint32_t)kB || (p.topo != 0 && p.topo != 1) || (p.rank_scope != 0 && p.rank_scope != 1) ||
       (p.rbf_policy != 0 && p.rbf_policy != 1) || p.max_rounds < 1 || p.max_rounds > kMaxRounds)
     return TOPOSZP_E_INVALID_ARG;
-  if (p.rank_scope == 1 && p.topo) return TOPOSZP_E_UNSUPPORTED;
-  if (out_cap < toposzp_compress_bound(ndim, dims)) return TOPOSZP_E_CAPACITY;
-  if (ws_bytes < ws_need(hg)) return TOPOSZP_E_CAPACITY;
+  const int field = p.rank_scope == 1 && p.topo ? 1 : 0;
+  if (field && !allow_field) return TOPOSZP_E_UNSUPPORTED;
+  if (out_cap < toposzp_compress_bound_ex(ndim, dims, field)) return TOPOSZP_E_CAPACITY;
+  if (ws_bytes < (field ? ws_need_field(hg) : ws_need(hg))) return TOPOSZP_E_CAPACITY;
 
   int nrange = (int)((hg.g.n / 4 + 256 * kRangeVec - 1) / (256 * kRangeVec));
   if (nrange > kRangeWG) nrange = kRangeWG;
@@ -2454,6 +2546,16 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   ea.eb = eb;
   ea.e_abs = e_abs;
   seg_layout(hg.nb, p.topo, 0, 0, ea.off, ea.len);
+  ea.field = field;
+  ea.keys = nullptr;
+  ea.vals = nullptr;
+  ea.delta = nullptr;
+  if (field) {
+    const FieldLayout F = field_layout(hg);
+    ea.keys = reinterpret_cast<unsigned long long*>(d_ws + F.keys_in);
+    ea.vals = reinterpret_cast<unsigned*>(d_ws + F.vals_in);
+    ea.delta = reinterpret_cast<const int*>(d_ws + F.delta);
+  }
 
   ScanArgs& sa = J->scan;
   sa.ws = d_ws;
@@ -2462,6 +2564,7 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   sa.nrange = nrange;
   sa.eb = eb;
   sa.e_abs = e_abs;
+  sa.field = field;
 
   FinArgs& fa = J->fin;
   fa.out = d_out;
@@ -2480,6 +2583,7 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   fa.e_abs = e_abs;
   fa.nrange = nrange;
   fa.fused = ea.nch <= kFuseMax ? 1 : 0;
+  fa.field = field;
   memcpy(fa.off, ea.off, sizeof(ea.off));
   memcpy(fa.len, ea.len, sizeof(ea.len));
   const double sig[3] = {0.5, 0.75, 1.0};
@@ -2607,6 +2711,19 @@ const char* toposzp_strerror(int status) {
   }
 }
 
+size_t toposzp_compress_bound_ex(uint32_t ndim, const uint64_t* dims, int32_t rank_scope) {
+  HostGeom hg;
+  if (host_geom(ndim, dims, &hg) != TOPOSZP_OK || (rank_scope != 0 && rank_scope != 1)) return 0;
+  uint64_t off[kNSeg], len[kNSeg];
+  return (size_t)seg_layout(hg.nb, 1, hg.nb * kMaxWData, hg.nb * (uint64_t)rank_w(rank_scope), off, len);
+}
+
+size_t toposzp_workspace_size_ex(uint32_t ndim, const uint64_t* dims, int32_t rank_scope) {
+  HostGeom hg;
+  if (host_geom(ndim, dims, &hg) != TOPOSZP_OK || (rank_scope != 0 && rank_scope != 1)) return 0;
+  return rank_scope ? ws_need_field(hg) : ws_need(hg);
+}
+
 size_t toposzp_compress_bound(uint32_t ndim, const uint64_t* dims) {
   HostGeom hg;
   if (host_geom(ndim, dims, &hg) != TOPOSZP_OK) return 0;
@@ -2648,7 +2765,33 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     ev_end(0, s);
   }
   ev_begin(1, s);
-  launch_encode((int)ndim, g_tune.encode_waves, xcd_grid(ea.nch), s, ea);
+  if (ea.field) {
+    // field-scope ranks: mark pass, sort by (class, bin, order), ranks, then
+    // the encode pass reading them
+    HostGeom hg;
+    (void)host_geom(ndim, dims, &hg);
+    const FieldLayout F = field_layout(hg);
+    uint8_t* ws = (uint8_t*)d_ws;
+    const unsigned grid = xcd_grid(ea.nch);
+    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
+    else hipLaunchKernelGGL((encode_kernel<2, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
+    size_t tb = F.tmp_bytes;
+    if (rocprim::radix_sort_pairs(ws + F.tmp, tb, reinterpret_cast<const unsigned long long*>(ws + F.keys_in),
+                                  reinterpret_cast<unsigned long long*>(ws + F.keys_out),
+                                  reinterpret_cast<const unsigned*>(ws + F.vals_in),
+                                  reinterpret_cast<unsigned*>(ws + F.vals_out), (unsigned)ea.gd.n, 0, 56,
+                                  s) != hipSuccess)
+      return TOPOSZP_E_DEVICE;
+    const unsigned rg = (unsigned)std::min<long long>(((long long)ea.gd.n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fs_rank_kernel, dim3(rg), dim3(256), 0, s,
+                       reinterpret_cast<const unsigned long long*>(ws + F.keys_out),
+                       reinterpret_cast<const unsigned*>(ws + F.vals_out), ea.gd.n,
+                       reinterpret_cast<int*>(ws + F.delta));
+    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
+    else hipLaunchKernelGGL((encode_kernel<2, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
+  } else {
+    launch_encode((int)ndim, g_tune.encode_waves, xcd_grid(ea.nch), s, ea);
+  }
   ev_end(1, s);
   ev_begin(2, s);
   if (!J.fin.fused) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, J.scan);
@@ -2736,7 +2879,7 @@ int toposzp_compress_batch(uint32_t count, const toposzp_compress_job* h_jobs, c
     const toposzp_compress_job& q = h_jobs[i];
     const size_t wsz = (i + 1 < count ? offs[i + 1] : need) - offs[i];
     const int rc = build_comp(q.d_field, q.ndim, q.dims, q.eb_mode, q.eb, params, ws + offs[i], wsz, q.d_out,
-                              q.out_cap, q.d_out_size, q.d_status, &jobs[i]);
+                              q.out_cap, q.d_out_size, q.d_status, &jobs[i], false);
     if (rc != TOPOSZP_OK) return rc;
     pre_r[i] = (int)nr;
     pre_c[i] = (int)nc;

@@ -62,7 +62,14 @@ def test_invalid_arguments_rejected_on_host(tsz):
     assert args(2, 0.1, 7, p) == tsz.E_INVALID_ARG
     assert args(2, 0.1, 0, tsz.Params(32, 0, 0, 16, 1)) == tsz.E_INVALID_ARG
     assert args(2, 0.1, 0, tsz.Params(64, 0, 0, 0, 1)) == tsz.E_INVALID_ARG
-    assert args(2, 0.1, 0, tsz.Params(64, 1, 0, 16, 1)) == tsz.E_UNSUPPORTED
+    assert args(2, 0.1, 0, tsz.Params(64, 2, 0, 16, 1)) == tsz.E_INVALID_ARG
+    # field-scope ranks need the larger workspace (checked before anything runs)
+    mid = (C.c_uint64 * 3)(1000, 1000, 1)
+    small = tsz.workspace_size((1000, 1000), 0)
+    assert tsz.workspace_size((1000, 1000), 1) > small
+    assert tsz.compress_bound((4, 4), 1) > tsz.compress_bound((4, 4), 0)
+    assert L.toposzp_compress(fake, 2, mid, 0, 0.1, C.byref(tsz.Params(64, 1, 0, 16, 1)), fake, small, fake,
+                              1 << 30, fake, fake, None) == tsz.E_CAPACITY
     big = (C.c_uint64 * 3)(1 << 16, 1 << 16, 1)
     assert L.toposzp_compress(fake, 2, big, 0, 0.1, C.byref(p), fake, 1 << 30, fake, 1 << 30, fake,
                               fake, None) == tsz.E_UNSUPPORTED

@@ -129,6 +129,26 @@ def test_parity_large_clusters(tsz, ora):
     check(tsz, ora, "checker_in_bumps", f, 2e-2, "rel")
 
 
+FIELD_SCOPE = [
+    ("bumps", lambda: datagen.gaussian_bumps_2d(96, 160, 10, seed=1), 1e-3, "rel"),
+    ("noise_abs", lambda: datagen.noise((77, 91), seed=5), 0.3, "abs"),
+    ("grf3d", lambda: datagen.grf_3d(20, 24, 28, seed=6), 1e-3, "abs"),
+    ("near_single_bin", lambda: datagen.noise((150, 170), seed=11), 2.5, "abs"),
+    ("ties", lambda: (np.round(datagen.noise((90, 130), seed=12) * 3) / 3).astype(np.float32), 0.2, "abs"),
+    ("tiny", lambda: datagen.noise((3, 3), seed=13), 0.5, "abs"),
+    ("cfg1_1800x3600_rel1e-3", datagen.cfg1, 1e-3, "rel"),
+]
+
+
+@pytest.mark.parametrize("name,gen,eb,mode", FIELD_SCOPE, ids=[c[0] for c in FIELD_SCOPE])
+def test_parity_field_scope(tsz, ora, name, gen, eb, mode):
+    # ranks among the flattened extrema of the whole field (sorted on the GPU)
+    res = check(tsz, ora, name + "_field", gen(), eb, mode, rank_scope=1)
+    assert res is not None
+    rc, info = ora.inspect(res[0])
+    assert rc == 0 and info["scope"] == 1
+
+
 def test_parity_plain_szp(tsz, ora):
     check(tsz, ora, "plain", datagen.gaussian_bumps_2d(90, 110, 5, seed=9), 1e-3, "rel", topo=False)
     check(tsz, ora, "plain3d", datagen.grf_3d(10, 12, 14, seed=9), 1e-3, "rel", topo=False)
