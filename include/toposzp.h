@@ -59,7 +59,10 @@ typedef struct {
   uint32_t block;     /* points per block; must be 64 (default 64) */
   int32_t rank_scope; /* 0 = ranks among flattened extrema of the same 64-point
                          block (default); 1 = whole field (needs the _ex sizes;
-                         not in the batched form: TOPOSZP_E_UNSUPPORTED there) */
+                         the call waits once on `stream` for the count of
+                         flattened extrema before it sorts them, so it returns
+                         after the preceding work on the stream; not in the
+                         batched form: TOPOSZP_E_UNSUPPORTED there) */
   int32_t rbf_policy; /* 0 = adaptive kernel size/width (default),
                          1 = always k_size 3 */
   int32_t max_rounds; /* cap on saddle-refinement rounds, 1..65535 (16) */

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
@@ -101,6 +102,7 @@ struct Ctrl {
   unsigned big;               // a cluster too large for a wave: whole-field replay
   unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
   Plan plan;
+  unsigned fs_count;          // field-scope compression: flattened extrema marked
 };
 static_assert(sizeof(Ctrl) <= 1024 - 16, "control block");
 
@@ -353,8 +355,10 @@ struct EncArgs {
   double eb;
   float e_abs;
   uint64_t off[kNSeg], len[kNSeg];
-  unsigned long long* keys;  // field scope: sort keys of the mark pass
+  unsigned long long* keys;  // field scope: compacted sort keys of the mark pass
   unsigned* vals;            // and their point indices
+  unsigned long long* skeys; // each wave's staging slice of keys (indexed like points)
+  unsigned* svals;           // and of indices
   const int* delta;          // field scope: ranks per point for the encode pass
 };
 
@@ -628,6 +632,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   bool wover = false;
 
   const unsigned lab_shift = 2u * (unsigned)(lane & 15);
+  int wcnt = 0;  // mark pass: entries in this wave's slice
   auto block = [&](const EncIn& in, int b) {
     const int lb = b - c * kB;
     if (b >= a.nb) {  // past the end (last chunk only)
@@ -703,15 +708,20 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     int delta = 0;
     if (MODE == kModeMark) {
       // sort key of each flattened extremum: class, bin, then the order in
-      // which less extreme values come first; every other point sorts last
+      // which less extreme values come first; packed into the wave's slice
       const unsigned long long ext = lostm & (m_min | m_max);
-      const bool ismax = lane_in(m_max);
-      const unsigned ord = (unsigned)(ismax ? fkey(av) : -fkey(av)) ^ 0x80000000u;
-      const unsigned long long key = ((unsigned long long)(ismax ? 1u : 0u) << 55) |
-                                     ((unsigned long long)(unsigned)(q + (1 << 22)) << 32) | ord;
-      if (i < n) {
-        a.keys[i] = lane_in(ext) ? key : ~0ull;
-        a.vals[i] = (unsigned)i;
+      if (ext) {
+        const bool ismax = lane_in(m_max);
+        const unsigned ord = (unsigned)(ismax ? fkey(av) : -fkey(av)) ^ 0x80000000u;
+        const unsigned long long key = ((unsigned long long)(ismax ? 1u : 0u) << 55) |
+                                       ((unsigned long long)(unsigned)(q + (1 << 22)) << 32) | ord;
+        if (lane_in(ext)) {
+          const int pos = wcnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(ext >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)ext, 0u));
+          a.skeys[(size_t)bw * kB + pos] = key;
+          a.svals[(size_t)bw * kB + pos] = (unsigned)i;
+        }
+        wcnt += __popcll(ext);
       }
       return;
     }
@@ -791,7 +801,27 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     block(P3, bw + k + 3);
     P3 = enc_fetch<ND>(f, min(bw + k + 7, blast), lane, g);
   }
-  if (MODE == kModeMark) return;  // the keys are written; the encode pass reports errors
+  if (MODE == kModeMark) {
+    // one range of the compacted arrays per workgroup from the field-wide
+    // counter; each wave then copies its slice there (the barrier makes the
+    // slices visible to the whole workgroup).  Errors are the encode pass's.
+    if (lane == 0) sh.pfd[wv] = wcnt;
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < WAVES; ++w) tot += sh.pfd[w];
+      sh.pfr[0] = tot ? (int)atomicAdd(&ctrl_of(a.ws)->fs_count, (unsigned)tot) : 0;
+    }
+    __syncthreads();
+    int off = sh.pfr[0];
+    for (int w = 0; w < wv; ++w) off += sh.pfd[w];
+    const size_t sb = (size_t)bw * kB;
+    for (int j = lane; j < wcnt; j += 64) {
+      a.keys[off + j] = a.skeys[sb + j];
+      a.vals[off + j] = a.svals[sb + j];
+    }
+    return;
+  }
   {
     const bool nf = nfm != 0, qo = qom != 0 || wover;
     if (lane == 0 && (nf || qo)) atomicOr(&sh.flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
@@ -884,6 +914,11 @@ __global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
   if (c < a.nch) encode_body<ND, WAVES, MODE>(a, c, sh);
 }
 
+// Clears the field-scope mark counter ahead of the mark pass.
+__global__ void fs_clear_kernel(uint8_t* ws) {
+  if (threadIdx.x == 0) ctrl_of(ws)->fs_count = 0;
+}
+
 // Field-scope ranks from the sorted keys: a flattened extremum's rank is 1 +
 // the number of entries of its (class, bin) group sorted before its value
 // (ties share a rank).  Both starts are lower bounds in the sorted prefix.
@@ -891,7 +926,6 @@ __global__ __launch_bounds__(256) void fs_rank_kernel(const unsigned long long* 
                                                       const unsigned* __restrict__ vals, int n, int* delta) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const unsigned long long k = keys[i];
-    if (k == ~0ull) continue;  // not a flattened extremum
     const unsigned long long gk = k & ~0xFFFFFFFFull;
     int lo = 0, hi = i;
     while (lo < hi) {
@@ -2549,11 +2583,16 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   ea.field = field;
   ea.keys = nullptr;
   ea.vals = nullptr;
+  ea.skeys = nullptr;
+  ea.svals = nullptr;
   ea.delta = nullptr;
   if (field) {
+    // the mark pass stages in the sort's output arrays, compacts into its input
     const FieldLayout F = field_layout(hg);
     ea.keys = reinterpret_cast<unsigned long long*>(d_ws + F.keys_in);
     ea.vals = reinterpret_cast<unsigned*>(d_ws + F.vals_in);
+    ea.skeys = reinterpret_cast<unsigned long long*>(d_ws + F.keys_out);
+    ea.svals = reinterpret_cast<unsigned*>(d_ws + F.vals_out);
     ea.delta = reinterpret_cast<const int*>(d_ws + F.delta);
   }
 
@@ -2766,27 +2805,40 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   }
   ev_begin(1, s);
   if (ea.field) {
-    // field-scope ranks: mark pass, sort by (class, bin, order), ranks, then
-    // the encode pass reading them
+    // field-scope ranks: the mark pass compacts the flattened extrema's sort
+    // keys; their count comes back to the host (the one synchronisation of
+    // this path), the keys are sorted by (class, bin, order) and ranked, and
+    // the encode pass reads the ranks
     HostGeom hg;
     (void)host_geom(ndim, dims, &hg);
     const FieldLayout F = field_layout(hg);
     uint8_t* ws = (uint8_t*)d_ws;
     const unsigned grid = xcd_grid(ea.nch);
+    hipLaunchKernelGGL(fs_clear_kernel, dim3(1), dim3(64), 0, s, ws);
     if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
     else hipLaunchKernelGGL((encode_kernel<2, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
-    size_t tb = F.tmp_bytes;
-    if (rocprim::radix_sort_pairs(ws + F.tmp, tb, reinterpret_cast<const unsigned long long*>(ws + F.keys_in),
-                                  reinterpret_cast<unsigned long long*>(ws + F.keys_out),
-                                  reinterpret_cast<const unsigned*>(ws + F.vals_in),
-                                  reinterpret_cast<unsigned*>(ws + F.vals_out), (unsigned)ea.gd.n, 0, 56,
-                                  s) != hipSuccess)
+    unsigned cnt = 0;
+    if (hipMemcpyAsync(&cnt, ws + offsetof(Ctrl, fs_count), sizeof cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
       return TOPOSZP_E_DEVICE;
-    const unsigned rg = (unsigned)std::min<long long>(((long long)ea.gd.n + 255) / 256, 4096);
-    hipLaunchKernelGGL(fs_rank_kernel, dim3(rg), dim3(256), 0, s,
-                       reinterpret_cast<const unsigned long long*>(ws + F.keys_out),
-                       reinterpret_cast<const unsigned*>(ws + F.vals_out), ea.gd.n,
-                       reinterpret_cast<int*>(ws + F.delta));
+    if ((uint64_t)cnt > (uint64_t)ea.gd.n) return TOPOSZP_E_DEVICE;
+    if (cnt) {
+      size_t tb = 0;
+      if (rocprim::radix_sort_pairs(nullptr, tb, (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                    (const unsigned*)nullptr, (unsigned*)nullptr, cnt, 0, 56, s) != hipSuccess)
+        return TOPOSZP_E_DEVICE;
+      if (tb > F.tmp_bytes) return TOPOSZP_E_CAPACITY;
+      if (rocprim::radix_sort_pairs(ws + F.tmp, tb, reinterpret_cast<const unsigned long long*>(ws + F.keys_in),
+                                    reinterpret_cast<unsigned long long*>(ws + F.keys_out),
+                                    reinterpret_cast<const unsigned*>(ws + F.vals_in),
+                                    reinterpret_cast<unsigned*>(ws + F.vals_out), cnt, 0, 56, s) != hipSuccess)
+        return TOPOSZP_E_DEVICE;
+      const unsigned rg = (unsigned)std::min<long long>(((long long)cnt + 255) / 256, 4096);
+      hipLaunchKernelGGL(fs_rank_kernel, dim3(rg), dim3(256), 0, s,
+                         reinterpret_cast<const unsigned long long*>(ws + F.keys_out),
+                         reinterpret_cast<const unsigned*>(ws + F.vals_out), (int)cnt,
+                         reinterpret_cast<int*>(ws + F.delta));
+    }
     if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
     else hipLaunchKernelGGL((encode_kernel<2, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
   } else {

@@ -129,6 +129,12 @@ def test_parity_large_clusters(tsz, ora):
     check(tsz, ora, "checker_in_bumps", f, 2e-2, "rel")
 
 
+def _all_lost(shape, seed):
+    rng = np.random.default_rng(seed)
+    par = np.indices(shape).sum(axis=0) % 2
+    return (0.5 + 0.01 * par + rng.uniform(0, 0.001, shape)).astype(np.float32)
+
+
 FIELD_SCOPE = [
     ("bumps", lambda: datagen.gaussian_bumps_2d(96, 160, 10, seed=1), 1e-3, "rel"),
     ("noise_abs", lambda: datagen.noise((77, 91), seed=5), 0.3, "abs"),
@@ -137,6 +143,11 @@ FIELD_SCOPE = [
     ("ties", lambda: (np.round(datagen.noise((90, 130), seed=12) * 3) / 3).astype(np.float32), 0.2, "abs"),
     ("tiny", lambda: datagen.noise((3, 3), seed=13), 0.5, "abs"),
     ("cfg1_1800x3600_rel1e-3", datagen.cfg1, 1e-3, "rel"),
+    # nothing flattened: the sort is skipped
+    ("none_lost", lambda: datagen.gaussian_bumps_2d(64, 80, 4, seed=2), 1e-7, "abs"),
+    # every point a flattened extremum (a jittered checkerboard inside one bin)
+    ("all_lost_2d", lambda: _all_lost((130, 150), seed=14), 0.1, "abs"),
+    ("all_lost_3d", lambda: _all_lost((17, 19, 23), seed=15), 0.1, "abs"),
 ]
 
 
