@@ -124,10 +124,12 @@ struct CompLayout {
 __host__ __device__ constexpr int rank_w(int field) { return field ? kMaxWRankAny : kMaxWRankBlk; }
 __host__ __device__ inline CompLayout comp_layout(uint64_t nch, int field = 0) {
   CompLayout L;
+  // three per-chunk arrays of u32, each padded to 16 bytes (read as uint4)
+  const uint64_t arr = (4 * nch + 15) & ~uint64_t(15);
   L.tot_d = kRegionOff;
-  L.tot_r = L.tot_d + 4 * nch;
-  L.cflag = L.tot_r + 4 * nch;
-  L.stage_d = al256(L.cflag + 4 * nch);
+  L.tot_r = L.tot_d + arr;
+  L.cflag = L.tot_r + arr;
+  L.stage_d = al256(L.cflag + arr);
   L.stage_r = al256(L.stage_d + 8ull * kB * kMaxWData * nch);
   L.end = al256(L.stage_r + 8ull * kB * rank_w(field) * nch);
   return L;
@@ -266,6 +268,19 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
   u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x142, 0xa, 0xf, false);
   u += (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x143, 0xc, 0xf, false);
   return (int)u;
+}
+// Sum and OR over the wave (uniform results).
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+  return (unsigned)__builtin_amdgcn_readlane((int)(unsigned)wave_incl_scan((int)v, 0), 63);
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 // Lane `l` (uniform) takes the uniform value `v`; other lanes keep `old`.
 __device__ __forceinline__ unsigned write_lane(unsigned old, unsigned v, int l) {
@@ -496,18 +511,31 @@ __global__ __launch_bounds__(256) void range_kernel(const float* __restrict__ f,
 }
 
 // Bound of the call (one wave): relative mode reduces the range partials.
-__device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_abs, int nrange,
-                           int lane, float* e, float* vmin, float* vmax, double* eps, bool* bad) {
+// LDS for the range reduction below (one slot per wave, up to 16 waves).
+struct RangeSh {
+  unsigned lo[16], hi[16], nf[16];
+};
+
+// The bound of this call (Section II-C).  A relative bound takes the field's
+// range from the range kernel's partials, reduced by the whole workgroup:
+// each thread loads up to four partials (blockDim.x >= kRangeWG / 4), the
+// waves combine through LDS.  Every thread gets the result.  It contains a
+// barrier: call it from workgroup-uniform control flow.
+__device__ __forceinline__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_abs, int nrange,
+                                           RangeSh& rs, float* e, float* vmin, float* vmax, double* eps, bool* bad) {
   unsigned lo = 0xFFFFFFFFu, hi = 0u, nf = 0u;
   if (eb_mode == TOPOSZP_EB_REL) {
-    // every partial load in flight at once (clamped indices repeat one)
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
     const uint4* part = reinterpret_cast<const uint4*>(ws + kPartOff);
 #pragma unroll
-    for (int t = 0; t < kRangeWG / 64; ++t) {
-      const uint4 p = part[min(lane + 64 * t, nrange - 1)];
-      lo = min(lo, p.x);
-      hi = max(hi, p.y);
-      nf |= p.z;
+    for (int t = 0; t < 4; ++t) {
+      const int j = tid + t * nt;
+      if (j < nrange) {
+        const uint4 p = part[j];
+        lo = min(lo, p.x);
+        hi = max(hi, p.y);
+        nf |= p.z;
+      }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -515,8 +543,17 @@ __device__ void call_bound(const uint8_t* ws, int eb_mode, double eb, float e_ab
       hi = max(hi, (unsigned)__shfl_xor((int)hi, o));
       nf |= (unsigned)__shfl_xor((int)nf, o);
     }
-  }
-  if (eb_mode == TOPOSZP_EB_REL) {
+    if (lane == 0) {
+      rs.lo[wv] = lo;
+      rs.hi[wv] = hi;
+      rs.nf[wv] = nf;
+    }
+    __syncthreads();
+    for (int w = 0; w < (nt >> 6); ++w) {
+      lo = min(lo, rs.lo[w]);
+      hi = max(hi, rs.hi[w]);
+      nf |= rs.nf[w];
+    }
     const float a = ukey2f(lo), b = ukey2f(hi);
     *vmin = a;
     *vmax = b;
@@ -581,6 +618,7 @@ struct EncSharedT {
   unsigned lab[kB * 4];
   int wd[kB], wr[kB];
   int pfd[kB + 1], pfr[kB + 1];
+  RangeSh rs;
   float e;
   unsigned flags;
 };
@@ -612,12 +650,12 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   EncIn P2 = enc_fetch<ND>(f, bw + 2, lane, g);
   EncIn P3 = enc_fetch<ND>(f, bw + 3, lane, g);
 
-  if (wv == 0) {
+  {
     float e, vmin, vmax;
     double eps;
     bool nf;
-    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
-    if (lane == 0) {
+    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, sh.rs, &e, &vmin, &vmax, &eps, &nf);
+    if (tid == 0) {
       sh.e = e;
       sh.flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
     }
@@ -665,11 +703,10 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       am[3] = __ballot(pc.y < g.ny - 1) & vm;
       am[4] = ND == 3 ? __ballot(pc.z > 0) & vm : 0ull;
       am[5] = ND == 3 ? __ballot(pc.z < g.nz - 1) & vm : 0ull;
-      unsigned long long gt[6], lt[6], gtr[6];
+      unsigned long long gt[6], lt[6];
 #pragma unroll
       for (int j = 0; j < 2 * ND; ++j) {
-        gtr[j] = __ballot(nb[j] > av);
-        gt[j] = gtr[j] & am[j];
+        gt[j] = __ballot(nb[j] > av) & am[j];
         lt[j] = __ballot(nb[j] < av) & am[j];
       }
       unsigned long long anyn = 0, notgt = 0, notlt = 0, pairs = vm, anybg = 0, anybl = 0;
@@ -690,14 +727,13 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       m_max = anyn & ~notlt;
       m_sad = pairs & anybg & anybl;
       // flattened by plain SZp iff some face neighbour shares the bin:
-      // -e <= a_n - 2qe < e, exact in double (see quantize); a higher
-      // neighbour can only share it from above, a lower one from below
+      // -e <= a_n - 2qe < e, exact in double (see quantize)
       const double c2 = (double)q * (2.0 * ed);
       unsigned long long same = 0;
 #pragma unroll
       for (int j = 0; j < 2 * ND; ++j) {
         const double d = (double)nb[j] - c2;
-        same |= am[j] & ((gtr[j] & __ballot(d < ed)) | (~gtr[j] & __ballot(d >= -ed)));
+        same |= am[j] & __ballot(d < ed) & __ballot(d >= -ed);
       }
       lostm = (m_min | m_max | m_sad) & same;
     }
@@ -1001,12 +1037,13 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
   for (int o = 32; o >= 1; o >>= 1) fl |= (unsigned)__shfl_xor((int)fl, o);
   if (lane == 0 && fl) atomicOr(&s_fl, fl);
   __syncthreads();
-  if (wv == 0) {
+  {
+    __shared__ RangeSh s_rs;
     float e, vmin, vmax;
     double eps;
     bool nf;
-    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
-    if (lane == 0) {
+    call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, s_rs, &e, &vmin, &vmax, &eps, &nf);
+    if (tid == 0) {
       unsigned flags = s_fl | (nf ? 1u : 0u);
       if (!(e >= 0x1p-100f && e <= 0x1p100f)) flags |= 2u;
       ct->tot_data = s_carry[0];
@@ -1032,6 +1069,7 @@ __device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); 
 // Places chunk c's staged planes; the last chunk also writes the header.
 __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   __shared__ uint8_t hdr[kHdr];
+  __shared__ uint64_t s_seg[2 * kNSeg];
   __shared__ unsigned s_sa[4], s_sb[4];
   __shared__ unsigned s_red[5][4];
   __shared__ unsigned s_flags;
@@ -1049,32 +1087,36 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     // td/tr hold per-chunk plane counts: every workgroup sums its
     // predecessors' (its offsets) and everybody's (the rank planes follow
     // all data planes); the last one also gathers the flags
+    // (four chunks per 16-byte load; the arrays are padded to 16 bytes)
     unsigned pd = 0, pr = 0, ad = 0, ar = 0, fl = 0;
-    for (int base = 0; base < a.nch; base += 256 * 8) {
+    const uint4* td4 = reinterpret_cast<const uint4*>(td);
+    const uint4* tr4 = reinterpret_cast<const uint4*>(tr);
+    const uint4* cf4 = reinterpret_cast<const uint4*>(cf);
+    const int n4 = (a.nch + 3) >> 2;
+    for (int j4 = tid; j4 < n4; j4 += 256) {
+      const uint4 vd = td4[j4], vr = tr4[j4];
+      const uint4 vf = last ? cf4[j4] : make_uint4(0u, 0u, 0u, 0u);
+      const unsigned d[4] = {vd.x, vd.y, vd.z, vd.w}, r[4] = {vr.x, vr.y, vr.z, vr.w};
+      const unsigned f[4] = {vf.x, vf.y, vf.z, vf.w};
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int j = base + t * 256 + tid;
-        const int jj = min(j, a.nch - 1);
-        const unsigned vd = td[jj], vr = tr[jj], vf = last ? cf[jj] : 0u;
+      for (int t = 0; t < 4; ++t) {
+        const int j = 4 * j4 + t;
         if (j < a.nch) {
-          ad += vd;
-          ar += vr;
-          fl |= vf;
+          ad += d[t];
+          ar += r[t];
+          fl |= f[t];
           if (j < c) {
-            pd += vd;
-            pr += vr;
+            pd += d[t];
+            pr += r[t];
           }
         }
       }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      pd += (unsigned)__shfl_xor((int)pd, o);
-      pr += (unsigned)__shfl_xor((int)pr, o);
-      ad += (unsigned)__shfl_xor((int)ad, o);
-      ar += (unsigned)__shfl_xor((int)ar, o);
-      fl |= (unsigned)__shfl_xor((int)fl, o);
-    }
+    pd = wave_sum(pd);
+    pr = wave_sum(pr);
+    ad = wave_sum(ad);
+    ar = wave_sum(ar);
+    fl = wave_or(fl);
     if (lane == 0) {
       s_red[0][wv] = pd;
       s_red[1][wv] = pr;
@@ -1082,12 +1124,13 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
       s_red[3][wv] = ar;
       s_red[4][wv] = fl;
     }
-    if (last && wv == 0) {
+    if (last) {
+      __shared__ RangeSh s_rs;
       float e, vmin, vmax;
       double eps;
       bool nf;
-      call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, lane, &e, &vmin, &vmax, &eps, &nf);
-      if (lane == 0) {
+      call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, s_rs, &e, &vmin, &vmax, &eps, &nf);
+      if (tid == 0) {
         s_e = e;
         s_vmin = vmin;
         s_vmax = vmax;
@@ -1148,7 +1191,9 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     int si = 0;
     if (a.rbf_policy == 0 && totd <= (uint64_t)a.nb) { k = 7; sigma = 1.0f; si = 2; }
     else if (a.rbf_policy == 0 && totd <= 3 * (uint64_t)a.nb) { k = 5; sigma = 0.75f; si = 1; }
-    uint64_t off[kNSeg], len[kNSeg];
+    // the segment table goes through LDS (registers would hold 26 words)
+    uint64_t* off = s_seg;
+    uint64_t* len = s_seg + kNSeg;
     const uint64_t total = seg_layout((uint64_t)a.nb, a.topo, totd, totr, off, len);
     hdr[0] = 'T'; hdr[1] = 'S'; hdr[2] = 'Z'; hdr[3] = '1';
     put2(hdr, 4, 1);
