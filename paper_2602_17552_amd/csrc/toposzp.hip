@@ -1843,17 +1843,18 @@ __device__ __forceinline__ void reach(const unsigned long long* bm, int p, Pt c,
 }
 
 constexpr int kClusterMax = 64;   // members of a cluster replayed in a workgroup
+static_assert(kClusterMax % 4 == 0, "member lists are read four at a time");
 #ifndef TSZ_REFINE_WAVES
 #define TSZ_REFINE_WAVES 2
 #endif
 constexpr int kRefThreads = 64 * TSZ_REFINE_WAVES;  // refine workgroup
 constexpr int kCandMax = 1024;                       // cluster owners per chunk per pass
-constexpr int kBatch = 32;                           // owners gathered at once
+constexpr int kBatch = 64;                           // owners gathered at once
 
 // LDS of the refine kernel.
 struct RefShared {
   unsigned cand[kCandMax];          // owners found in phase A
-  unsigned memb[kBatch][kClusterMax];  // their clusters
+  alignas(16) unsigned memb[kBatch][kClusterMax];  // their clusters
   unsigned msize[kBatch];           // member count; 0 = not an owner or too large
   unsigned off[kBatch + 1];         // first lane of each cluster in the pack
   unsigned cflag[kBatch];           // bit0 still running, bit1 committed this round
@@ -1880,8 +1881,15 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
     const Around<ND, K> ar(cc, g);
     const bool far = far_from_ends<ND>(cur, g);
     auto add = [&](int q) {
+      // already a member? (four members per 16-byte read; mem is 16-byte
+      // aligned and holds kClusterMax entries, a multiple of 4)
       bool seen = false;
-      for (unsigned j = 0; j < m; ++j) seen |= mem[j] == (unsigned)q;
+      const uint4* m4 = reinterpret_cast<const uint4*>(mem);
+      for (unsigned j = 0; j < m; j += 4) {
+        const uint4 w = m4[j >> 2];
+        seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
+                (j + 3 < m && w.w == (unsigned)q);
+      }
       if (seen) return;
       if ((unsigned)q < p0) owner = false;
       if (m == (unsigned)kClusterMax) *over = true;
@@ -2377,7 +2385,7 @@ __device__ __forceinline__ void for_items(int T, Fn&& fn) {
   }
 }
 
-__global__ __launch_bounds__(256) void range_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(256) void range_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
   const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
@@ -2389,7 +2397,7 @@ __global__ __launch_bounds__(256) void range_batch_kernel(const uint8_t* tab) {
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t* __restrict__ tab) {
   __shared__ EncShared sh;
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr)) + h->count + 1;
@@ -2402,7 +2410,7 @@ __global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t*
   });
 }
 
-__global__ __launch_bounds__(1024) void scan_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(1024) void scan_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
   for_items(h->count, [&](int f) {
@@ -2410,7 +2418,7 @@ __global__ __launch_bounds__(1024) void scan_batch_kernel(const uint8_t* tab) {
   });
 }
 
-__global__ __launch_bounds__(256) void finalize_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(256) void finalize_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr)) + h->count + 1;
   const CompJob* jobs = reinterpret_cast<const CompJob*>(tab + tab_jobs_off(h->count));
@@ -2421,7 +2429,7 @@ __global__ __launch_bounds__(256) void finalize_batch_kernel(const uint8_t* tab)
 }
 
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void decode_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(8))) void decode_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
   const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
@@ -2432,7 +2440,7 @@ __global__ __launch_bounds__(WAVES * 64) void decode_batch_kernel(const uint8_t*
 }
 
 __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_batch_kernel(
-    const uint8_t* tab) {
+    const uint8_t* __restrict__ tab) {
   __shared__ RefShared sh;
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr));
@@ -2443,7 +2451,7 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
   });
 }
 
-__global__ __launch_bounds__(1024) void tail_batch_kernel(const uint8_t* tab) {
+__global__ __launch_bounds__(1024) void tail_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
   for_items(h->count, [&](int f) { tail_body(jobs[f].ref); });
