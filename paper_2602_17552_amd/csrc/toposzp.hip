@@ -943,8 +943,10 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   }
 }
 
+// At most 96 SGPRs: eight waves per SIMD instead of seven (a few values then
+// live in VGPR lanes), which measures about 4% faster.
 template <int ND, int WAVES, int MODE = kModeBlock>
-__global__ __launch_bounds__(WAVES * 64) void encode_kernel(EncArgs a) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_num_sgpr(96))) void encode_kernel(EncArgs a) {
   __shared__ EncSharedT<MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk> sh;
   const int c = xcd_chunk(blockIdx.x, a.nch);
   if (c < a.nch) encode_body<ND, WAVES, MODE>(a, c, sh);
