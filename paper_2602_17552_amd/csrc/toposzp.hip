@@ -167,6 +167,12 @@ __device__ __forceinline__ float key2f(long long k) {
   unsigned b = k >= 0 ? (unsigned)k : 0x80000000u + (unsigned)(-k);
   return __int_as_float((int)b);
 }
+__device__ __forceinline__ float key2f32(int k) {
+  if (k > 0x7F800000) k = 0x7F800001;
+  if (k < -0x7F800000) k = -0x7F800001;
+  const unsigned b = k >= 0 ? (unsigned)k : 0x80000000u + (0u - (unsigned)k);
+  return __int_as_float((int)b);
+}
 __device__ __forceinline__ unsigned ukey(float x) { return (unsigned)fkey(x) ^ 0x80000000u; }
 __device__ __forceinline__ float ukey2f(unsigned u) { return key2f((int)(u ^ 0x80000000u)); }
 
@@ -1543,8 +1549,17 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
       if (valid && dl > 0 && (lab == CLS_MIN || lab == CLS_MAX)) {
         // flattened extremum: its neighbour maximum (minimum) is its own bin
         // centre, so the stencil value is delta float steps beyond it
-        const long long kk = (long long)fkey(rq) + (lab == CLS_MAX ? (long long)dl : -(long long)dl);
-        const float cand = key2f(kk);
+        float cand;
+        if (h.scope == 0) {
+          // block scope: delta <= 64, and the key of a finite float lies well
+          // inside int32, so the 32-bit sum is exact (a corrupt delta only
+          // wraps; the call then reports the stream corrupt)
+          const int kk = (int)((unsigned)fkey(rq) + (unsigned)(lab == CLS_MAX ? dl : -dl));
+          cand = key2f32(kk);
+        } else {
+          const long long kk = (long long)fkey(rq) + (lab == CLS_MAX ? (long long)dl : -(long long)dl);
+          cand = key2f(kk);
+        }
         if (fabs((double)cand - (double)rq) <= ed) {
           v = cand;
           ++moves;
