@@ -306,29 +306,26 @@ __device__ __forceinline__ unsigned mbcnt(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// Bit length of the largest of the lanes' values (each < 2^31): a binary
-// search with one lane-mask test per step, steps of 2^(S-1) .. 1.
-template <int S>
+// Bit length of the largest of the lanes' values: the highest set bit of
+// their OR is the largest value's (an OR over the wave, then one scalar
+// find-last-bit).
 __device__ __forceinline__ int wave_bitlen(unsigned v) {
-  int L = 0;
-#pragma unroll
-  for (int s = 1 << (S - 1); s >= 1; s >>= 1)
-    if (__ballot(v >= (1u << (L + s - 1)))) L += s;
-  return L;
+  const unsigned o = wave_or(v);
+  return o ? 32 - __builtin_clz(o) : 0;
 }
 
 // B + LZ + BE of one 64-value block held one value per lane: residuals
 // r_0 = 0, r_i = v_i - v_{i-1}; width = bit length of max |r_i|; the sign and
 // each bit plane are one 64-bit lane mask; plane j goes to dst[2j], dst[2j+1]
-// (LDS) through lanes 2j, 2j+1.  S: search steps of the width (2^S > MAXW).
-template <int MAXW, int S>
+// (LDS) through lanes 2j, 2j+1.
+template <int MAXW>
 __device__ __forceinline__ int encode_block(int v, int lane, unsigned* dst,
                                             unsigned long long& sign, int& first, bool& over) {
   const int prev = dpp_from_prev(v, v);  // lane 0 sees itself: residual 0
   const int r = v - prev;                // |v| < 2^23: no overflow
   sign = __ballot(r < 0);
   const unsigned mag = (unsigned)(r < 0 ? -r : r);
-  int w = wave_bitlen<S>(mag);
+  int w = wave_bitlen(mag);
   if (w > MAXW) {
     over = true;
     w = MAXW;
@@ -803,7 +800,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
 
     unsigned long long sign;
     int first;
-    const int w = encode_block<kMaxWData, 5>(q, lane, sh.pd[lb], sign, first, wover);
+    const int w = encode_block<kMaxWData>(q, lane, sh.pd[lb], sign, first, wover);
     if (lane == 0) {
       sh.wd[lb] = w;
       sh.sign[lb] = sign;
@@ -819,7 +816,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       unsigned long long rsign;
       int rfirst;
       bool rover = false;
-      const int wr = encode_block<MAXWR, MAXWR == kMaxWRankBlk ? 3 : 5>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
+      const int wr = encode_block<MAXWR>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
       if (lane == 0) {
         sh.wr[lb] = wr;
         sh.rsign[lb] = rsign;
