@@ -17,7 +17,9 @@
  *    otherwise).
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls are stream-ordered and asynchronous: results are valid once the
- *    stream has been synchronised.  Nothing is read back to the host.
+ *    stream has been synchronised.  Nothing is read back to the host except
+ *    where a call says so (field-scope compression, the stats calls, the
+ *    autotuners).
  *  - The return value is a status: TOPOSZP_OK (0) or a negative error from
  *    the list below, detected on the host before anything is enqueued.
  *    Errors that only the device can see (non-finite input, values out of
@@ -27,7 +29,8 @@
  *    3D = {nz, ny, nx}; x varies fastest.  A field holds at most 2^31 - 1
  *    points.
  *  - One workspace serves one call at a time: calls that share a workspace
- *    must be ordered on one stream.
+ *    must be ordered on one stream.  Calls on different workspaces may be
+ *    issued from several host threads at once.
  *  - No exception crosses the ABI.
  */
 #ifndef TOPOSZP_H
@@ -205,7 +208,8 @@ int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job 
 /* Launch shapes used by every call of this process (they change no byte of
  * any result): waves per workgroup of the encode and decode kernels (4 or 8)
  * and the persistent grid of the batched form in workgroups per compute
- * unit (1..32).  Defaults {4, 4, 8, 8}. */
+ * unit (1..32).  Defaults {4, 4, 8, 8}.  Calls on other host threads read
+ * either the old or the new set, never a mix. */
 typedef struct {
   int32_t encode_waves, decode_waves, compress_wgs_per_cu, decompress_wgs_per_cu;
 } toposzp_tuning;
@@ -232,7 +236,8 @@ int toposzp_inspect(const uint8_t *h_hdr, size_t n, toposzp_info *out);
  * [4] flattened extrema left in place by the error budget. */
 int toposzp_decompress_stats(const void *d_ws, int64_t out[5], void *stream);
 
-/* Per-kernel timing with HIP events on the call's stream (diagnostics).
+/* Per-kernel timing with HIP events on the call's stream (a diagnostic for
+ * one host thread and one device: the events are shared by all calls).
  * While enabled, each call records events around its kernels; after the
  * stream is synchronised toposzp_kernel_times fills ms[] for the last
  * compress and decompress: [0] range pass, [1] encode, [2] finalize,

@@ -40,6 +40,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -2513,8 +2514,8 @@ float host_round_down(double d) {
   return f;
 }
 
-// timing
-bool g_timing = false;
+// timing (a diagnostic for one host thread: the events are shared)
+std::atomic<bool> g_timing{false};
 hipEvent_t g_ev[6][2];
 bool g_ev_used[6];
 bool g_ev_init = false;
@@ -2569,8 +2570,18 @@ size_t ws_need_n(uint64_t n) {
   return (size_t)al256(c > d ? c : d);
 }
 
-// Launch shapes (they change no byte of any result).
-toposzp_tuning g_tune = {4, 4, 8, 8};
+// Launch shapes (they change no byte of any result), one byte each in one
+// word, so that a call on any host thread reads a consistent set.
+std::atomic<uint32_t> g_tune{4u | 4u << 8 | 8u << 16 | 8u << 24};
+toposzp_tuning tune_now() {
+  const uint32_t w = g_tune.load(std::memory_order_relaxed);
+  return {(int32_t)(w & 255u), (int32_t)(w >> 8 & 255u), (int32_t)(w >> 16 & 255u), (int32_t)(w >> 24)};
+}
+void tune_set(const toposzp_tuning& t) {
+  g_tune.store((uint32_t)t.encode_waves | (uint32_t)t.decode_waves << 8 | (uint32_t)t.compress_wgs_per_cu << 16 |
+                   (uint32_t)t.decompress_wgs_per_cu << 24,
+               std::memory_order_relaxed);
+}
 
 bool tuning_ok(const toposzp_tuning& t) {
   auto wgs = [](int v) { return v >= 1 && v <= 32; };
@@ -2578,16 +2589,16 @@ bool tuning_ok(const toposzp_tuning& t) {
          wgs(t.compress_wgs_per_cu) && wgs(t.decompress_wgs_per_cu);
 }
 
-int g_cus[64];
+std::atomic<int> g_cus[64];  // compute units per device, 0 until first asked
 int cu_count() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!g_cus[dev]) {
-    int c = 0;
+  int c = g_cus[dev].load(std::memory_order_relaxed);
+  if (!c) {
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
-    g_cus[dev] = c;
+    g_cus[dev].store(c, std::memory_order_relaxed);
   }
-  return g_cus[dev];
+  return c;
 }
 
 // Persistent grid: wgs_per_cu workgroups per CU, a multiple of 8, at most
@@ -2767,12 +2778,12 @@ int autotune(const std::vector<toposzp_tuning>& cands, hipStream_t s, Run&& run,
     (void)hipEventDestroy(e0);
     return TOPOSZP_E_DEVICE;
   }
-  const toposzp_tuning saved = g_tune;
+  const toposzp_tuning saved = tune_now();
   toposzp_tuning best = saved;
   float best_ms = 1e30f;
   int rc = TOPOSZP_OK;
   for (const toposzp_tuning& t : cands) {
-    g_tune = t;
+    tune_set(t);
     float ms[5];
     for (int r = 0; r < 7 && rc == TOPOSZP_OK; ++r) {
       if (r >= 2 && hipEventRecord(e0, s) != hipSuccess) rc = TOPOSZP_E_DEVICE;
@@ -2792,8 +2803,8 @@ int autotune(const std::vector<toposzp_tuning>& cands, hipStream_t s, Run&& run,
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  g_tune = rc == TOPOSZP_OK ? best : saved;
-  if (out) *out = g_tune;
+  tune_set(rc == TOPOSZP_OK ? best : saved);
+  if (out) *out = tune_now();
   return rc;
 }
 
@@ -2864,7 +2875,8 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   if (rc != TOPOSZP_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   const EncArgs& ea = J.enc;
-  for (int k = 0; k < 3; ++k) g_ev_used[k] = false;
+  if (g_timing)
+    for (int k = 0; k < 3; ++k) g_ev_used[k] = false;
   if (eb_mode == TOPOSZP_EB_REL) {
     ev_begin(0, s);
     hipLaunchKernelGGL(range_kernel, dim3(ea.nrange), dim3(256), 0, s, d_field, ea.gd.n, (uint8_t*)d_ws);
@@ -2909,7 +2921,7 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
     else hipLaunchKernelGGL((encode_kernel<2, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
   } else {
-    launch_encode((int)ndim, g_tune.encode_waves, xcd_grid(ea.nch), s, ea);
+    launch_encode((int)ndim, tune_now().encode_waves, xcd_grid(ea.nch), s, ea);
   }
   ev_end(1, s);
   ev_begin(2, s);
@@ -2926,9 +2938,10 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   const int rc = build_dec(d_in, in_size, d_out, out_cap_elems, (uint8_t*)d_ws, ws_bytes, d_status, &J, &slots);
   if (rc != TOPOSZP_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  for (int k = 3; k < 5; ++k) g_ev_used[k] = false;
+  if (g_timing)
+    for (int k = 3; k < 5; ++k) g_ev_used[k] = false;
   ev_begin(3, s);
-  if (g_tune.decode_waves == 8)
+  if (tune_now().decode_waves == 8)
     hipLaunchKernelGGL(decode_kernel<8>, dim3(slots), dim3(512), 0, s, J.dec);
   else
     hipLaunchKernelGGL(decode_kernel<4>, dim3(slots), dim3(256), 0, s, J.dec);
@@ -3015,9 +3028,10 @@ int toposzp_compress_batch(uint32_t count, const toposzp_compress_job* h_jobs, c
   h->n_slot = 0;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(ws, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TOPOSZP_E_DEVICE;
-  const int wpc = g_tune.compress_wgs_per_cu;
+  const toposzp_tuning tn = tune_now();
+  const int wpc = tn.compress_wgs_per_cu;
   if (nr > 0) hipLaunchKernelGGL(range_batch_kernel, dim3(batch_grid((int)nr, wpc)), dim3(256), 0, s, ws);
-  if (g_tune.encode_waves == 8)
+  if (tn.encode_waves == 8)
     hipLaunchKernelGGL(encode_batch_kernel<8>, dim3(batch_grid((int)nc, wpc)), dim3(512), 0, s, ws);
   else
     hipLaunchKernelGGL(encode_batch_kernel<4>, dim3(batch_grid((int)nc, wpc)), dim3(256), 0, s, ws);
@@ -3059,8 +3073,9 @@ int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job* h_job
   h->n_slot = (int)ns;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(ws, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TOPOSZP_E_DEVICE;
-  const int wpc = g_tune.decompress_wgs_per_cu;
-  if (g_tune.decode_waves == 8)
+  const toposzp_tuning tn = tune_now();
+  const int wpc = tn.decompress_wgs_per_cu;
+  if (tn.decode_waves == 8)
     hipLaunchKernelGGL(decode_batch_kernel<8>, dim3(batch_grid((int)ns, wpc)), dim3(512), 0, s, ws);
   else
     hipLaunchKernelGGL(decode_batch_kernel<4>, dim3(batch_grid((int)ns, wpc)), dim3(256), 0, s, ws);
@@ -3080,13 +3095,13 @@ int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job*
 
 int toposzp_set_tuning(const toposzp_tuning* t) {
   if (!t || !tuning_ok(*t)) return TOPOSZP_E_INVALID_ARG;
-  g_tune = *t;
+  tune_set(*t);
   return TOPOSZP_OK;
 }
 
 int toposzp_get_tuning(toposzp_tuning* t) {
   if (!t) return TOPOSZP_E_INVALID_ARG;
-  *t = g_tune;
+  *t = tune_now();
   return TOPOSZP_OK;
 }
 
@@ -3094,8 +3109,9 @@ int toposzp_autotune_compress_batch(uint32_t count, const toposzp_compress_job* 
                                     const toposzp_params* params, void* d_ws, size_t ws_bytes, void* stream,
                                     toposzp_tuning* out) {
   std::vector<toposzp_tuning> c;
+  const toposzp_tuning cur = tune_now();
   for (int w : {4, 8})
-    for (int g : {2, 4, 8, 16}) c.push_back({w, g_tune.decode_waves, g, g_tune.decompress_wgs_per_cu});
+    for (int g : {2, 4, 8, 16}) c.push_back({w, cur.decode_waves, g, cur.decompress_wgs_per_cu});
   return autotune(c, (hipStream_t)stream,
                   [&]() { return toposzp_compress_batch(count, h_jobs, params, d_ws, ws_bytes, stream); }, out);
 }
@@ -3103,8 +3119,9 @@ int toposzp_autotune_compress_batch(uint32_t count, const toposzp_compress_job* 
 int toposzp_autotune_decompress_batch(uint32_t count, const toposzp_decompress_job* h_jobs, void* d_ws,
                                       size_t ws_bytes, void* stream, toposzp_tuning* out) {
   std::vector<toposzp_tuning> c;
+  const toposzp_tuning cur = tune_now();
   for (int w : {4, 8})
-    for (int g : {2, 4, 8, 16}) c.push_back({g_tune.encode_waves, w, g_tune.compress_wgs_per_cu, g});
+    for (int g : {2, 4, 8, 16}) c.push_back({cur.encode_waves, w, cur.compress_wgs_per_cu, g});
   return autotune(c, (hipStream_t)stream,
                   [&]() { return toposzp_decompress_batch(count, h_jobs, d_ws, ws_bytes, stream); }, out);
 }
