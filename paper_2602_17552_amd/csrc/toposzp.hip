@@ -1882,9 +1882,14 @@ struct RefShared {
 // saddle reachable through read-set offsets.  Returns the member count, or
 // 0 if a smaller member exists (it owns the cluster) or there are more than
 // kClusterMax members (*over set).
+template <int K>
+__device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
+                             bool* over);
+
 template <int ND, int K>
 __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
                            bool* over) {
+  if constexpr (ND == 2) return gather2d<K>(bm, p0, g, mem, over);
   using H = Hood<ND, K>;
   mem[0] = p0;
   unsigned m = 1;
@@ -1941,6 +1946,95 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
     } else {
 #pragma unroll
       for (int dz = -H::RZ; dz <= H::RZ; ++dz) plane(dz);
+    }
+  }
+  return owner && !*over ? m : 0u;
+}
+
+// The same gather for 2D fields, with the bitmap rows of the next queued
+// member requested while the current member's rows are scanned (members
+// away from the first and last rows only), so that the queue's steps do not
+// each wait a full load round trip.
+template <int K>
+__device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
+                             bool* over) {
+  using H = Hood<2, K>;
+  constexpr int NR = 2 * H::R + 1;
+  mem[0] = p0;
+  unsigned m = 1;
+  bool owner = true;
+  *over = false;
+  auto add = [&](int q) {
+    // already a member? (four members per 16-byte read; mem is 16-byte
+    // aligned and holds kClusterMax entries, a multiple of 4)
+    bool seen = false;
+    const uint4* m4 = reinterpret_cast<const uint4*>(mem);
+    for (unsigned j = 0; j < m; j += 4) {
+      const uint4 w = m4[j >> 2];
+      seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
+              (j + 3 < m && w.w == (unsigned)q);
+    }
+    if (seen) return;
+    if ((unsigned)q < p0) owner = false;
+    if (m == (unsigned)kClusterMax) *over = true;
+    else mem[m++] = (unsigned)q;
+  };
+  // the two bitmap words holding bits [p + dy nx - R, p + dy nx + R] of
+  // each row dy (p away from the first and last rows: every index >= 0)
+  auto fetch = [&](int p, unsigned long long (&w)[NR][2]) {
+#pragma unroll
+    for (int dy = -H::R; dy <= H::R; ++dy) {
+      const int lo = p + dy * g.nx - H::R;
+      w[dy + H::R][0] = bm[lo >> 6];
+      w[dy + H::R][1] = bm[(lo >> 6) + 1];
+    }
+  };
+  unsigned long long cw[NR][2];
+  bool have = false;  // cw holds the rows of the member at the head
+  for (unsigned head = 0; head < m && owner && !*over; ++head) {
+    const int cur = (int)mem[head];
+    const Pt cc = coords_of(cur, g);
+    const Around<2, K> ar(cc, g);
+    const bool far = far_from_ends<2>(cur, g);
+    unsigned bits[NR];
+    if (far) {
+      if (!have) fetch(cur, cw);
+#pragma unroll
+      for (int dy = -H::R; dy <= H::R; ++dy) {
+        unsigned rm = 0;
+#pragma unroll
+        for (int dx = -H::R; dx <= H::R; ++dx)
+          if (H::read(dx, dy, 0) && !(dx == 0 && dy == 0) && ar.in(dx, dy, 0)) rm |= 1u << (dx + H::R);
+        const int sh = (cur + dy * g.nx - H::R) & 63;
+        const unsigned long long w0 = cw[dy + H::R][0], w1 = cw[dy + H::R][1];
+        bits[dy + H::R] = (unsigned)(sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0) & rm;
+      }
+    }
+    // the next member's rows go out before this member's cells are added
+    have = false;
+    if (head + 1 < m) {
+      const int nxt = (int)mem[head + 1];
+      if (far_from_ends<2>(nxt, g)) {
+        fetch(nxt, cw);
+        have = true;
+      }
+    }
+    if (far) {
+#pragma unroll
+      for (int dy = -H::R; dy <= H::R; ++dy) {
+        const int row = cur + dy * g.nx;
+        for (unsigned b = bits[dy + H::R]; b; b &= b - 1) add(row + __builtin_ctz(b) - H::R);
+      }
+    } else {
+#pragma unroll
+      for (int dy = -H::R; dy <= H::R; ++dy)
+#pragma unroll
+        for (int dx = -H::R; dx <= H::R; ++dx) {
+          if (!H::read(dx, dy, 0) || (dx == 0 && dy == 0)) continue;
+          const bool in = ar.in(dx, dy, 0);
+          const int q = in ? cur + dy * g.nx + dx : cur;
+          if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q);
+        }
     }
   }
   return owner && !*over ? m : 0u;
