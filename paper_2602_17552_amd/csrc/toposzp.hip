@@ -1863,6 +1863,7 @@ static_assert(kClusterMax % 4 == 0, "member lists are read four at a time");
 #define TSZ_REFINE_WAVES 2
 #endif
 constexpr int kRefThreads = 64 * TSZ_REFINE_WAVES;  // refine workgroup
+static_assert(kRefThreads <= kChunk, "one queue slot per refine thread");
 constexpr int kCandMax = 1024;                       // cluster owners per chunk per pass
 constexpr int kBatch = 64;                           // owners gathered at once
 
@@ -2055,6 +2056,9 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
   const GeomD& g = pl.g;
   const int cap = pl.max_rounds;
 
+  // the first entry of this thread, read beside the count (the chunk's
+  // kChunk queue slots always exist; an entry past the count is not used)
+  const unsigned first = idx[tid];
   for (unsigned base = 0; base < cnt; base += kCandMax) {
     // phase A, one lane per queued saddle: isolated saddles are settled by
     // one evaluation; a saddle with no smaller queued saddle in reach owns
@@ -2063,7 +2067,7 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
     __syncthreads();
     const unsigned lim = min(cnt, base + kCandMax);
     for (unsigned t = base + tid; t < lim; t += kRefThreads) {
-      const int p = (int)idx[t];
+      const int p = (int)(t == (unsigned)tid ? first : idx[t]);
       const Pt pc = coords_of(p, g);
       // the reach test and the evaluation read disjoint data: both go out
       // at once, and the evaluation counts only for an isolated saddle

@@ -256,7 +256,9 @@ FULL = [
     ("cfg1_1800x3600_rel1e-2", datagen.cfg1, 1e-2),
     ("cfg1_1800x3600_rel1e-3", datagen.cfg1, 1e-3),
     ("cfg1_1800x3600_rel1e-4", datagen.cfg1, 1e-4),
+    ("cfg1_1800x3600_rel5e-2_k7", datagen.cfg1, 5e-2),   # the widest window, at scale
     ("cfg2_256cube_rel1e-3", datagen.cfg2, 1e-3),
+    ("cfg2_256cube_rel3e-2_k5", datagen.cfg2, 3e-2),     # a 3D k=5 window, at scale
 ]
 _cache = {}
 
