@@ -41,6 +41,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -89,6 +90,7 @@ struct Plan {                 // decode -> refine/tail hand-off
   GeomD g;
   float e;
   float w[10];
+  double wsum;  // the window's weight sum when every cell lies in the grid
   uint64_t s6_off;
 };
 
@@ -1416,6 +1418,20 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
       p.g.dy = make_div((unsigned)p.g.ny);
       p.e = h.e;
       for (int d2 = 0; d2 < 10; ++d2) p.w[d2] = h.w[d2];
+      // the candidate's weight sum for a window wholly inside the grid, added
+      // in the candidate's own (dz, dy, dx) order
+      {
+        const int r = p.k / 2, rz = p.ndim == 3 ? r : 0;
+        double ws = 0.0;
+        for (int dz = -rz; dz <= rz; ++dz)
+          for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+              const int d2 = dz * dz + dy * dy + dx * dx;
+              if (d2 == 0 || d2 > r * r) continue;
+              ws = ws + (double)p.w[d2];
+            }
+        p.wsum = ws;
+      }
       p.s6_off = h.off[S6];
     }
   }
@@ -1739,46 +1755,58 @@ __device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels,
   const float p0 = v[CZ][2][2];
   if (cls(0, 0, 0, p0) == CLS_SAD) return 1;
   // normalised Gaussian window without p, in (dz, dy, dx) order; cells
-  // outside the grid carry weight 0, which leaves both sums unchanged
+  // outside the grid carry weight 0, which leaves both sums unchanged.  A
+  // window wholly inside the grid skips the range tests, and its weight sum
+  // is the plan's (the same additions in the same order).
   constexpr int rz = ND == 3 ? r : 0;
   double num = 0.0, den = 0.0;
-  auto plane = [&](int dz) {
-#pragma unroll
-    for (int dy = -r; dy <= r; ++dy)
-#pragma unroll
-      for (int dx = -r; dx <= r; ++dx) {
-        const int d2 = dz * dz + dy * dy + dx * dx;
-        if (d2 == 0 || d2 > r * r) continue;
-        const bool in = ar.in(dx, dy, dz);
-        const bool core = Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) <= 2;
-        const float x = core ? v[dz + CZ][dy + 2][dx + 2] : fld[in ? p + dz * g.nxy + dy * g.nx + dx : p];
-        const double wt = in ? (double)pl.w[d2] : 0.0;
+  const bool inside = ar.in(-r, -r, -rz) && ar.in(r, r, rz);
+  auto sum = [&](auto all_in) {
+    constexpr bool AI = decltype(all_in)::value;
+    auto cell = [&](int dx, int dy, int dz, float x) {
+      const int d2 = dz * dz + dy * dy + dx * dx;
+      if (AI) {
+        num = num + (double)pl.w[d2] * (double)x;
+      } else {
+        const double wt = ar.in(dx, dy, dz) ? (double)pl.w[d2] : 0.0;
         num = num + wt * (double)x;
         den = den + wt;
       }
-  };
-  if constexpr (ND == 3 && K == 7) {
-    // planes in turn (a runtime loop keeps one plane's loads in registers);
-    // every cell of these planes is read from memory
+    };
+    auto at = [&](int dx, int dy, int dz) {
+      return fld[AI || ar.in(dx, dy, dz) ? p + dz * g.nxy + dy * g.nx + dx : p];
+    };
+    if constexpr (ND == 3 && K == 7) {
+      // planes in turn (a runtime loop keeps one plane's loads in
+      // registers); every cell of these planes is read from memory
 #pragma unroll 1
-    for (int dz = -rz; dz <= rz; ++dz) {
+      for (int dz = -rz; dz <= rz; ++dz) {
 #pragma unroll
-      for (int dy = -r; dy <= r; ++dy)
+        for (int dy = -r; dy <= r; ++dy)
 #pragma unroll
-        for (int dx = -r; dx <= r; ++dx) {
-          const int d2 = dz * dz + dy * dy + dx * dx;
-          if (d2 == 0 || d2 > r * r) continue;
-          const bool in = ar.in(dx, dy, dz);
-          const float x = fld[in ? p + dz * g.nxy + dy * g.nx + dx : p];
-          const double wt = in ? (double)pl.w[d2] : 0.0;
-          num = num + wt * (double)x;
-          den = den + wt;
-        }
+          for (int dx = -r; dx <= r; ++dx) {
+            const int d2 = dz * dz + dy * dy + dx * dx;
+            if (d2 == 0 || d2 > r * r) continue;
+            cell(dx, dy, dz, at(dx, dy, dz));
+          }
+      }
+    } else {
+#pragma unroll
+      for (int dz = -rz; dz <= rz; ++dz)
+#pragma unroll
+        for (int dy = -r; dy <= r; ++dy)
+#pragma unroll
+          for (int dx = -r; dx <= r; ++dx) {
+            const int d2 = dz * dz + dy * dy + dx * dx;
+            if (d2 == 0 || d2 > r * r) continue;
+            const bool core = Hood<ND, K>::iabs(dx) + Hood<ND, K>::iabs(dy) + Hood<ND, K>::iabs(dz) <= 2;
+            cell(dx, dy, dz, core ? v[dz + CZ][dy + 2][dx + 2] : at(dx, dy, dz));
+          }
     }
-  } else {
-#pragma unroll
-    for (int dz = -rz; dz <= rz; ++dz) plane(dz);
-  }
+    if (AI) den = pl.wsum;
+  };
+  if (inside) sum(std::true_type{});
+  else sum(std::false_type{});
   if (den == 0.0) return 0;
   const float cand = (float)(num / den);
   if (!(fabs((double)cand - (double)p0) <= (double)pl.e)) return 0;
