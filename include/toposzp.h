@@ -208,7 +208,7 @@ int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job 
 /* Launch shapes used by every call of this process (they change no byte of
  * any result): waves per workgroup of the encode and decode kernels (4 or 8)
  * and the persistent grid of the batched form in workgroups per compute
- * unit (1..32).  Defaults {4, 4, 8, 8}.  Calls on other host threads read
+ * unit (1..32).  Defaults {8, 4, 8, 8}.  Calls on other host threads read
  * either the old or the new set, never a mix. */
 typedef struct {
   int32_t encode_waves, decode_waves, compress_wgs_per_cu, decompress_wgs_per_cu;
