@@ -1564,17 +1564,24 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
         // flattened extremum: its neighbour maximum (minimum) is its own bin
         // centre, so the stencil value is delta float steps beyond it
         float cand;
+        bool fits;
         if (h.scope == 0) {
           // block scope: delta <= 64, and the key of a finite float lies well
           // inside int32, so the 32-bit sum is exact (a corrupt delta only
-          // wraps; the call then reports the stream corrupt)
+          // wraps; the call then reports the stream corrupt).  At most 64
+          // steps from a bin centre (0, or at least 2e >= 2^-99 in size) the
+          // candidate keeps the centre's sign and lies within a factor 2 of
+          // it, so their float difference is exact (Sterbenz) and the budget
+          // test needs no double
           const int kk = (int)((unsigned)fkey(rq) + (unsigned)(lab == CLS_MAX ? dl : -dl));
           cand = key2f32(kk);
+          fits = fabsf(cand - rq) <= h.e;
         } else {
           const long long kk = (long long)fkey(rq) + (lab == CLS_MAX ? (long long)dl : -(long long)dl);
           cand = key2f(kk);
+          fits = fabs((double)cand - (double)rq) <= ed;
         }
-        if (fabs((double)cand - (double)rq) <= ed) {
+        if (fits) {
           v = cand;
           ++moves;
         } else {
