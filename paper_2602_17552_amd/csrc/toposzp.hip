@@ -360,6 +360,47 @@ __device__ __forceinline__ int decode_block(PlanePtr planes, int w, int first, u
   return wave_incl_scan(r, lane);
 }
 
+// Two blocks at once (as decode_block each): their plane reads and prefix
+// sums are independent chains that the scheduler interleaves.
+template <typename PlanePtr>
+__device__ __forceinline__ void decode_pair(PlanePtr pa, int wa, int fa, unsigned long long sa, PlanePtr pb, int wb,
+                                            int fb, unsigned long long sb, int lane, int& qa, int& qb) {
+  const auto ua = reinterpret_cast<const unsigned*>(pa) + (lane >> 5);
+  const auto ub = reinterpret_cast<const unsigned*>(pb) + (lane >> 5);
+  const unsigned sh = (unsigned)lane & 31u;
+  unsigned ma = 0, mb = 0;
+  const int wc = wa < wb ? wa : wb;
+  int j = 0;
+#pragma unroll 2
+  for (; j < wc; ++j) {
+    ma |= ((ua[2 * j] >> sh) & 1u) << j;
+    mb |= ((ub[2 * j] >> sh) & 1u) << j;
+  }
+  for (int t = j; t < wa; ++t) ma |= ((ua[2 * t] >> sh) & 1u) << t;
+  for (int t = j; t < wb; ++t) mb |= ((ub[2 * t] >> sh) & 1u) << t;
+  int ra = ((sa >> lane) & 1ull) ? (int)(0u - ma) : (int)ma;
+  int rb = ((sb >> lane) & 1ull) ? (int)(0u - mb) : (int)mb;
+  if (lane == 0) {
+    ra = fa;
+    rb = fb;
+  }
+  unsigned x = (unsigned)ra, y = (unsigned)rb;
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x111, 0xf, 0xf, false);
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x112, 0xf, 0xf, false);
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x114, 0xf, 0xf, false);
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x118, 0xf, 0xf, false);
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x142, 0xa, 0xf, false);
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  y += (unsigned)__builtin_amdgcn_update_dpp(0, (int)y, 0x143, 0xc, 0xf, false);
+  qa = (int)x;
+  qb = (int)y;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel arguments.
 
@@ -1543,20 +1584,16 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
   unsigned* qi = reinterpret_cast<unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
   bool corrupt = false;
   unsigned moves = 0, skips = 0;
-  for (int k = 0; k < BPW; ++k) {
-    const int lb = wv * BPW + k;
+  // one block's work once its values (q) and ranks (dl) are decoded
+  auto finish = [&](int lb, int q, int dl) {
     const uint64_t b = (uint64_t)c * kB + lb;
-    if (b >= h.nb) break;
     const int i = (int)(b * kB) + lane;
     const bool valid = i < n;
-    const int q = decode_block(s_pl + s_pfd[lb], s_wd[lb], s_first[lb], s_sign[lb], lane);
     corrupt |= valid && (q > kQMax || q < -kQMax);
     const float rq = (float)q * two_e;  // float(2q) * e: the same exact product
     float v = rq;
     bool queue = false;
     if (topo) {
-      const int dl = rank_lds ? decode_block(s_rpl + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], lane)
-                              : decode_block(rglob + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], lane);
       corrupt |= valid && (dl < 0 || dl > dmax);
       const unsigned lw = s_lab[4 * lb + (lane >> 4)];
       const int lab = valid ? (int)((lw >> (2 * (lane & 15))) & 3u) : CLS_R;
@@ -1599,6 +1636,29 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
       }
     }
     if (valid) a.out[i] = v;
+  };
+  // blocks two at a time (BPW is even): the pair's plane reads and prefix
+  // sums interleave; a pair past the end of the field keeps its first block
+  static_assert(BPW % 2 == 0, "blocks in pairs");
+  for (int k = 0; k < BPW; k += 2) {
+    const int lb = wv * BPW + k;
+    const uint64_t b = (uint64_t)c * kB + lb;
+    if (b >= h.nb) break;
+    const bool two = b + 1 < h.nb;
+    int q0, q1, d0 = 0, d1 = 0;
+    decode_pair(s_pl + s_pfd[lb], s_wd[lb], s_first[lb], s_sign[lb], s_pl + s_pfd[lb + 1], two ? s_wd[lb + 1] : 0,
+                s_first[lb + 1], s_sign[lb + 1], lane, q0, q1);
+    if (topo) {
+      const int wr1 = two ? s_wr[lb + 1] : 0;
+      if (rank_lds)
+        decode_pair(s_rpl + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], s_rpl + s_pfr[lb + 1], wr1,
+                    s_rfirst[lb + 1], s_rsign[lb + 1], lane, d0, d1);
+      else
+        decode_pair(rglob + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], rglob + s_pfr[lb + 1], wr1,
+                    s_rfirst[lb + 1], s_rsign[lb + 1], lane, d0, d1);
+    }
+    finish(lb, q0, d0);
+    if (two) finish(lb + 1, q1, d1);
   }
   const bool cb = __ballot(corrupt) != 0;
 #pragma unroll
