@@ -9,7 +9,7 @@
  * extraction (MD), the extrema stencil (CP+RP) and the RBF refinement of lost
  * saddles (RS) with the guard against new or changed critical points.
  *
- * Readings of points the paper leaves open (each also listed in the design doc):
+ * Readings of points the paper leaves open:
  *  - QZ: bin q is the unique integer with (2q-1)e <= a < (2q+1)e, i.e.
  *    floor((a+e)/(2e)) in exact arithmetic (Section II-C formula); the
  *    reconstruction is the bin centre, float(2q) * e, rounded once
