@@ -137,8 +137,12 @@ def lib():
 
 
 def _dims(shape):
+    if len(shape) not in (2, 3):
+        raise ValueError(f"fields are 2D or 3D, got shape {tuple(shape)}")
     arr = (C.c_uint64 * 3)(1, 1, 1)
     for k, d in enumerate(shape):
+        if int(d) < 1:
+            raise ValueError(f"every extent must be >= 1, got shape {tuple(shape)}")
         arr[k] = int(d)
     return arr
 

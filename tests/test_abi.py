@@ -95,3 +95,11 @@ def test_inspect_oracle_stream(tsz, ora):
     bad = bytearray(bytes(s[:512]))
     bad[20] ^= 1
     assert tsz.inspect(bytes(bad))[0] == tsz.E_CORRUPT
+
+
+def test_binding_rejects_bad_shapes(tsz):
+    for shape in [(5,), (2, 3, 4, 5), (0, 7), (3, -1)]:
+        with pytest.raises(ValueError):
+            tsz.compress_bound(shape)
+        with pytest.raises(ValueError):
+            tsz.workspace_size(shape)
