@@ -1959,12 +1959,13 @@ static_assert(kClusterMax % 4 == 0, "member lists are read four at a time");
 #endif
 constexpr int kRefThreads = 64 * TSZ_REFINE_WAVES;  // refine workgroup
 static_assert(kRefThreads <= kChunk, "one queue slot per refine thread");
-constexpr int kCandMax = 1024;                       // cluster owners per chunk per pass
+constexpr int kCandMax = 512;                        // queued saddles per chunk per pass
 constexpr int kBatch = 64;                           // owners gathered at once
 
 // LDS of the refine kernel.
 struct RefShared {
   unsigned cand[kCandMax];          // owners found in phase A
+  unsigned vis[kBatch][8];          // per gathering lane: members in a 16x16 window around its owner (2D)
   alignas(16) unsigned memb[kBatch][kClusterMax];  // their clusters
   unsigned msize[kBatch];           // member count; 0 = not an owner or too large
   unsigned off[kBatch + 1];         // first lane of each cluster in the pack
@@ -1980,12 +1981,13 @@ struct RefShared {
 // kClusterMax members (*over set).
 template <int K>
 __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
-                             bool* over);
+                             unsigned* vis, bool* over);
 
 template <int ND, int K>
 __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
-                           bool* over) {
-  if constexpr (ND == 2) return gather2d<K>(bm, p0, g, mem, over);
+                           unsigned* vis, bool* over) {
+  if constexpr (ND == 2) return gather2d<K>(bm, p0, g, mem, vis, over);
+  (void)vis;
   using H = Hood<ND, K>;
   mem[0] = p0;
   unsigned m = 1;
@@ -2050,27 +2052,42 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
 // The same gather for 2D fields, with the bitmap rows of the next queued
 // member requested while the current member's rows are scanned (members
 // away from the first and last rows only), so that the queue's steps do not
-// each wait a full load round trip.
+// each wait a full load round trip.  Membership of a cell within a 16x16
+// window around the owner is one bit of `vis` (8 words); only cells outside
+// it are looked up in the member list.
 template <int K>
 __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
-                             bool* over) {
+                             unsigned* vis, bool* over) {
   using H = Hood<2, K>;
   constexpr int NR = 2 * H::R + 1;
   mem[0] = p0;
   unsigned m = 1;
   bool owner = true;
   *over = false;
-  auto add = [&](int q) {
-    // already a member? (four members per 16-byte read; mem is 16-byte
-    // aligned and holds kClusterMax entries, a multiple of 4)
-    bool seen = false;
-    const uint4* m4 = reinterpret_cast<const uint4*>(mem);
-    for (unsigned j = 0; j < m; j += 4) {
-      const uint4 w = m4[j >> 2];
-      seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
-              (j + 3 < m && w.w == (unsigned)q);
+  const Pt oc = coords_of((int)p0, g);
+#pragma unroll
+  for (int w = 0; w < 8; ++w) vis[w] = 0u;
+  vis[(8 * 16 + 8) >> 5] = 1u << ((8 * 16 + 8) & 31);  // the owner
+  // q at grid coordinates (qx, qy)
+  auto add = [&](int q, int qx, int qy) {
+    const int rx = qx - oc.x + 8, ry = qy - oc.y + 8;
+    if ((unsigned)rx < 16u && (unsigned)ry < 16u) {
+      const unsigned bit = (unsigned)(ry * 16 + rx), mk = 1u << (bit & 31u);
+      const unsigned w = vis[bit >> 5];
+      if (w & mk) return;
+      vis[bit >> 5] = w | mk;
+    } else {
+      // already a member? (four members per 16-byte read; mem is 16-byte
+      // aligned and holds kClusterMax entries, a multiple of 4)
+      bool seen = false;
+      const uint4* m4 = reinterpret_cast<const uint4*>(mem);
+      for (unsigned j = 0; j < m; j += 4) {
+        const uint4 w = m4[j >> 2];
+        seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
+                (j + 3 < m && w.w == (unsigned)q);
+      }
+      if (seen) return;
     }
-    if (seen) return;
     if ((unsigned)q < p0) owner = false;
     if (m == (unsigned)kClusterMax) *over = true;
     else mem[m++] = (unsigned)q;
@@ -2119,7 +2136,10 @@ __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const Ge
 #pragma unroll
       for (int dy = -H::R; dy <= H::R; ++dy) {
         const int row = cur + dy * g.nx;
-        for (unsigned b = bits[dy + H::R]; b; b &= b - 1) add(row + __builtin_ctz(b) - H::R);
+        for (unsigned b = bits[dy + H::R]; b; b &= b - 1) {
+          const int dx = __builtin_ctz(b) - H::R;
+          add(row + dx, cc.x + dx, cc.y + dy);
+        }
       }
     } else {
 #pragma unroll
@@ -2129,7 +2149,7 @@ __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const Ge
           if (!H::read(dx, dy, 0) || (dx == 0 && dy == 0)) continue;
           const bool in = ar.in(dx, dy, 0);
           const int q = in ? cur + dy * g.nx + dx : cur;
-          if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q);
+          if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q, cc.x + dx, cc.y + dy);
         }
     }
   }
@@ -2190,7 +2210,7 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
       const unsigned nbat = min(nc - b0, (unsigned)kBatch);
       if ((unsigned)tid < nbat) {
         bool over;
-        sh.msize[tid] = gather<ND, K>(bm, sh.cand[b0 + tid], g, sh.memb[tid], &over);
+        sh.msize[tid] = gather<ND, K>(bm, sh.cand[b0 + tid], g, sh.memb[tid], sh.vis[tid], &over);
         if (over) atomicOr(&ctrl_of(a.ws)->big, 1u);  // left to the whole-field replay
       }
       __syncthreads();
