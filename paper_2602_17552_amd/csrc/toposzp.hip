@@ -94,6 +94,8 @@ struct Plan {                 // decode -> refine/tail hand-off
   uint64_t s6_off;
 };
 
+constexpr int kOverMax = 128;  // owner candidates of over-size clusters kept for the tail
+
 struct Ctrl {
   // compression: written by scan_kernel, read by finalize_kernel
   unsigned long long tot_data, tot_rank;
@@ -102,10 +104,11 @@ struct Ctrl {
   double eps;
   // decompression
   unsigned hflags;            // header check of this call: 0 good, 1 corrupt, 2 capacity
-  unsigned big;               // a cluster too large for a wave: whole-field replay
+  unsigned big;               // owner candidates whose cluster was too large for a workgroup
   unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
   Plan plan;
   unsigned fs_count;          // field-scope compression: flattened extrema marked
+  unsigned over[kOverMax];    // the first kOverMax of those candidates
 };
 static_assert(sizeof(Ctrl) <= 1024 - 16, "control block");
 
@@ -2211,7 +2214,11 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
       if ((unsigned)tid < nbat) {
         bool over;
         sh.msize[tid] = gather<ND, K>(bm, sh.cand[b0 + tid], g, sh.memb[tid], sh.vis[tid], &over);
-        if (over) atomicOr(&ctrl_of(a.ws)->big, 1u);  // left to the whole-field replay
+        if (over) {  // left to the tail, which gathers such clusters from these candidates
+          Ctrl* ct = ctrl_of(a.ws);
+          const unsigned k = atomicAdd(&ct->big, 1u);
+          if (k < (unsigned)kOverMax) ct->over[k] = sh.cand[b0 + tid];
+        }
       }
       __syncthreads();
       for (unsigned k0 = 0; k0 < nbat;) {
@@ -2343,10 +2350,11 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
 }
 
 // Whole-field replay of the schedule over every queued saddle, by one
-// workgroup with workgroup barriers.  Runs only when some cluster was too
-// large for a wave; clusters already settled by the refine kernel neither
-// commit nor change here (their inputs are unchanged), so only the large
-// ones progress.  Returns the rounds run; commits go to stats[1].
+// workgroup with workgroup barriers.  Runs only when the clusters too large
+// for the refine kernel do not fit the tail's LDS; clusters already settled
+// by the refine kernel neither commit nor change here (their inputs are
+// unchanged), so only the large ones progress.  Returns the rounds run;
+// commits go to stats[1].
 template <int ND, int K>
 __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout& L) {
   __shared__ unsigned s_commits;
@@ -2407,12 +2415,159 @@ __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout
   return (unsigned)min(round, pl.max_rounds);
 }
 
+// The over-size clusters, gathered and replayed by the tail workgroup from
+// LDS.  Clusters are independent of each other (no member lies in another
+// cluster's read set), so replaying only these runs the same schedule on
+// them as the whole-field replay, and leaves every other point as the refine
+// kernel left it.
+constexpr int kTailMax = 4096;             // members the tail holds
+constexpr int kTailHash = 2 * kTailMax;    // open-addressing set of those members
+constexpr unsigned kTailEmpty = 0xffffffffu;
+
+struct TailShared {
+  unsigned mem[kTailMax];
+  union {
+    unsigned hash[kTailHash];  // while gathering
+    struct {
+      float pend[kTailMax];
+      uint8_t state[kTailMax];  // 0 open, 1 settled, 2 commit pending
+    } r;                        // while replaying
+  };
+  unsigned nm, fail, commits;
+};
+
+// Gathers every queued saddle connected to one of the ns seeds, level by
+// level.  Returns the member count, or 0 when they do not fit (the field is
+// left untouched then).
+template <int ND, int K>
+__device__ unsigned gather_over(const unsigned long long* bm, const GeomD& g, const unsigned* seeds,
+                                unsigned ns, TailShared& t) {
+  using H = Hood<ND, K>;
+  const unsigned tid = threadIdx.x, nthr = blockDim.x;
+  for (unsigned i = tid; i < (unsigned)kTailHash; i += nthr) t.hash[i] = kTailEmpty;
+  if (tid == 0) {
+    t.nm = 0;
+    t.fail = 0;
+  }
+  __syncthreads();
+  // adds q unless present; every probe sequence is bounded by the table size
+  auto insert = [&](unsigned q) {
+    unsigned h = (q * 2654435761u) & (unsigned)(kTailHash - 1);
+    for (int n = 0; n < kTailHash; ++n) {
+      const unsigned old = atomicCAS(&t.hash[h], kTailEmpty, q);
+      if (old == kTailEmpty) {
+        const unsigned sl = atomicAdd(&t.nm, 1u);
+        if (sl < (unsigned)kTailMax) t.mem[sl] = q;
+        else t.fail = 1;
+        return;
+      }
+      if (old == q) return;
+      h = (h + 1) & (unsigned)(kTailHash - 1);
+    }
+    t.fail = 1;
+  };
+  for (unsigned i = tid; i < ns; i += nthr) insert(seeds[i]);
+  __syncthreads();
+  unsigned lo = 0;
+  for (;;) {
+    // the level's bounds, read by every thread before anyone inserts
+    const unsigned hi = min(t.nm, (unsigned)kTailMax);
+    const bool fail = t.fail != 0;
+    __syncthreads();
+    if (fail) return 0;
+    if (lo == hi) return hi;
+    for (unsigned i = lo + tid; i < hi; i += nthr) {
+      const int cur = (int)t.mem[i];
+      const Pt cc = coords_of(cur, g);
+#pragma unroll 1
+      for (int dz = -H::RZ; dz <= H::RZ; ++dz) {
+        if ((unsigned)(cc.z + dz) >= (unsigned)g.nz) continue;
+#pragma unroll 1
+        for (int dy = -H::R; dy <= H::R; ++dy) {
+          if ((unsigned)(cc.y + dy) >= (unsigned)g.ny) continue;
+          for (int dx = -H::R; dx <= H::R; ++dx) {
+            if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
+            if ((unsigned)(cc.x + dx) >= (unsigned)g.nx) continue;
+            const int q = cur + dz * g.nxy + dy * g.nx + dx;
+            if ((bm[q >> 6] >> (q & 63)) & 1ull) insert((unsigned)q);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    lo = hi;
+  }
+}
+
+// The colour-phased Jacobi schedule over the nm gathered members.  Returns
+// the rounds run; the commits go to stats[1].
+template <int ND, int K>
+__device__ unsigned replay_list(const RefArgs& a, const Plan& pl, TailShared& t, unsigned nm) {
+  const uint8_t* labels = a.in + pl.s6_off;
+  const unsigned tid = threadIdx.x, nthr = blockDim.x;
+  for (unsigned i = tid; i < nm; i += nthr) t.r.state[i] = 0;
+  __syncthreads();
+  int round = 1;
+  unsigned long long total = 0;
+  for (; round <= pl.max_rounds; ++round) {
+    if (tid == 0) t.commits = 0;
+    __syncthreads();
+    for (int ph = 0; ph < pl.ncol; ++ph) {
+      for (unsigned i = tid; i < nm; i += nthr) {
+        if (t.r.state[i]) continue;
+        const int p = (int)t.mem[i];
+        const Pt pc = coords_of(p, pl.g);
+        if (colour_of(pc, ND) != ph) continue;
+        float v;
+        const int res = evaluate<ND, K>(a.out, labels, p, pc, pl, &v);
+        if (res == 1) {
+          t.r.state[i] = 1;
+        } else if (res == 2) {
+          t.r.pend[i] = v;
+          t.r.state[i] = 2;
+          atomicAdd(&t.commits, 1u);
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+      for (unsigned i = tid; i < nm; i += nthr)
+        if (t.r.state[i] == 2) {
+          a.out[t.mem[i]] = t.r.pend[i];
+          t.r.state[i] = 1;
+        }
+      __threadfence_block();
+      __syncthreads();
+    }
+    const unsigned commits = t.commits;
+    __syncthreads();
+    total += commits;
+    if (commits == 0) break;
+  }
+  if (tid == 0) ctrl_of(a.ws)->stats[1] = total;
+  return (unsigned)min(round, pl.max_rounds);
+}
+
+// Replays the over-size clusters from the recorded candidates; false (with
+// nothing changed) when there are more candidates or members than the tail
+// holds, and the whole-field replay has to run instead.
+template <int ND, int K>
+__device__ bool replay_over(const RefArgs& a, const Plan& pl, const DecLayout& L, unsigned ncand,
+                            TailShared& t, unsigned* rounds) {
+  if (ncand > (unsigned)kOverMax) return false;
+  const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
+  const unsigned nm = gather_over<ND, K>(bm, pl.g, ctrl_of(a.ws)->over, ncand, t);
+  if (!nm) return false;
+  *rounds = replay_list<ND, K>(a, pl, t, nm);
+  return true;
+}
+
 // Status and counters of the decompression (one workgroup), after the
-// whole-field replay when a cluster needed it.
+// replay of the clusters too large for the refine kernel, if any.
 __device__ __forceinline__ void tail_body(const RefArgs& a) {
   __shared__ Plan s_p;
   __shared__ unsigned s_big, s_ok, s_hf, s_fl, s_rounds;
   __shared__ unsigned long long s_sum[4];
+  __shared__ TailShared s_t;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -2432,13 +2587,26 @@ __device__ __forceinline__ void tail_body(const RefArgs& a) {
   const DecLayout L = dec_layout(nb, ok ? (uint64_t)pl.nch : 0);
   unsigned trounds = 0;
   if (ok && pl.topo && s_big) {
+    const unsigned nc = s_big;
     switch (pl.ndim * 8 + pl.k) {
-      case 2 * 8 + 3: trounds = replay_all<2, 3>(a, pl, L); break;
-      case 2 * 8 + 5: trounds = replay_all<2, 5>(a, pl, L); break;
-      case 2 * 8 + 7: trounds = replay_all<2, 7>(a, pl, L); break;
-      case 3 * 8 + 3: trounds = replay_all<3, 3>(a, pl, L); break;
-      case 3 * 8 + 5: trounds = replay_all<3, 5>(a, pl, L); break;
-      default: trounds = replay_all<3, 7>(a, pl, L); break;
+      case 2 * 8 + 3:
+        if (!replay_over<2, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 3>(a, pl, L);
+        break;
+      case 2 * 8 + 5:
+        if (!replay_over<2, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 5>(a, pl, L);
+        break;
+      case 2 * 8 + 7:
+        if (!replay_over<2, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 7>(a, pl, L);
+        break;
+      case 3 * 8 + 3:
+        if (!replay_over<3, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 3>(a, pl, L);
+        break;
+      case 3 * 8 + 5:
+        if (!replay_over<3, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 5>(a, pl, L);
+        break;
+      default:
+        if (!replay_over<3, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 7>(a, pl, L);
+        break;
     }
   }
   __syncthreads();

@@ -115,9 +115,20 @@ def test_parity_kernel_sizes(tsz, ora):
     assert len(ks) >= 3
 
 
+def _checker_patches(m, counts, gap=4):
+    # checker_3d blocks of m^3 cells, `gap` constant cells apart (beyond any
+    # read set): one cluster of queued saddles per block at coarse bounds
+    p = m + gap
+    f = np.zeros(tuple(c * p for c in counts), np.float32)
+    for n, (i, j, k) in enumerate(np.ndindex(*counts)):
+        f[p * i:p * i + m, p * j:p * j + m, p * k:p * k + m] = datagen.checker_3d(m, m, m, seed=100 + n)
+    return f
+
+
 def test_parity_large_clusters(tsz, ora):
-    # queued saddles linked into clusters of hundreds of members (beyond one
-    # wave), with commits: the whole-field replay path
+    # queued saddles linked into clusters beyond the refine workgroup's 64
+    # members (the 3D checker: one of several hundred), with commits:
+    # replayed by the tail from LDS
     res = check(tsz, ora, "checker2d", datagen.checker_2d(40, 48, seed=0), 2.0, "abs")
     assert res[2]["commits"] > 0
     res = check(tsz, ora, "checker3d", datagen.checker_3d(10, 12, 14, seed=11), 1.0, "abs")
@@ -127,6 +138,23 @@ def test_parity_large_clusters(tsz, ora):
     f = datagen.gaussian_bumps_2d(120, 150, 12, seed=9)
     f[30:70, 40:88] = datagen.checker_2d(40, 48, seed=1) * 0.05 + f[30:70, 40:88]
     check(tsz, ora, "checker_in_bumps", f, 2e-2, "rel")
+
+
+def test_parity_tail_clusters(tsz, ora):
+    # thirty separate over-size clusters, gathered together by the tail
+    res = check(tsz, ora, "patches30", _checker_patches(6, (2, 3, 5)), 1.0, "abs")
+    assert 30 * 40 < res[2]["worklist0"] < 4096
+
+
+def test_parity_whole_field_replay(tsz, ora):
+    # over-size clusters beyond what the tail holds in LDS: the whole-field
+    # replay.  One cluster of more than 4096 queued saddles ...
+    res = check(tsz, ora, "checker3d_big", datagen.checker_3d(24, 26, 28, seed=1), 1.0, "abs")
+    assert res[2]["worklist0"] > 4096
+    # ... and 150 over-size clusters, more than the 128 candidates the
+    # refine kernel records
+    res = check(tsz, ora, "patches150", _checker_patches(7, (5, 5, 6)), 1.0, "abs")
+    assert res[2]["worklist0"] > 150 * 65
 
 
 def _all_lost(shape, seed):
