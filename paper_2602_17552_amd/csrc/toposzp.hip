@@ -1968,7 +1968,7 @@ constexpr int kBatch = 64;                           // owners gathered at once
 // LDS of the refine kernel.
 struct RefShared {
   unsigned cand[kCandMax];          // owners found in phase A
-  unsigned vis[kBatch][8];          // per gathering lane: members in a 16x16 window around its owner (2D)
+  unsigned vis[kBatch][8];          // per gathering lane: members in a 256-cell window at its owner
   alignas(16) unsigned memb[kBatch][kClusterMax];  // their clusters
   unsigned msize[kBatch];           // member count; 0 = not an owner or too large
   unsigned off[kBatch + 1];         // first lane of each cluster in the pack
@@ -1986,32 +1986,48 @@ template <int K>
 __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
                              unsigned* vis, bool* over);
 
+// In 3D, membership of a cell within a 4x8x8 window (the owner's plane and
+// the 3 after it, 4 rows and columns either side; members lie at larger
+// indices) is one bit of `vis` (8 words); cells outside it are looked up in
+// the member list.
 template <int ND, int K>
 __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
                            unsigned* vis, bool* over) {
   if constexpr (ND == 2) return gather2d<K>(bm, p0, g, mem, vis, over);
-  (void)vis;
   using H = Hood<ND, K>;
   mem[0] = p0;
   unsigned m = 1;
   bool owner = true;
   *over = false;
+  const Pt oc = coords_of((int)p0, g);
+#pragma unroll
+  for (int w = 0; w < 8; ++w) vis[w] = 0u;
+  vis[(4 * 8 + 4) >> 5] = 1u << ((4 * 8 + 4) & 31);  // the owner
   for (unsigned head = 0; head < m && owner && !*over; ++head) {
     const int cur = (int)mem[head];
     const Pt cc = coords_of(cur, g);
     const Around<ND, K> ar(cc, g);
     const bool far = far_from_ends<ND>(cur, g);
-    auto add = [&](int q) {
-      // already a member? (four members per 16-byte read; mem is 16-byte
-      // aligned and holds kClusterMax entries, a multiple of 4)
-      bool seen = false;
-      const uint4* m4 = reinterpret_cast<const uint4*>(mem);
-      for (unsigned j = 0; j < m; j += 4) {
-        const uint4 w = m4[j >> 2];
-        seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
-                (j + 3 < m && w.w == (unsigned)q);
+    // q at offset (dx, dy, dz) from the current member
+    auto add = [&](int q, int dx, int dy, int dz) {
+      const int rx = cc.x + dx - oc.x + 4, ry = cc.y + dy - oc.y + 4, rz = cc.z + dz - oc.z;
+      if ((unsigned)rx < 8u && (unsigned)ry < 8u && (unsigned)rz < 4u) {
+        const unsigned bit = (unsigned)((rz * 8 + ry) * 8 + rx), mk = 1u << (bit & 31u);
+        const unsigned w = vis[bit >> 5];
+        if (w & mk) return;
+        vis[bit >> 5] = w | mk;
+      } else {
+        // already a member? (four members per 16-byte read; mem is 16-byte
+        // aligned and holds kClusterMax entries, a multiple of 4)
+        bool seen = false;
+        const uint4* m4 = reinterpret_cast<const uint4*>(mem);
+        for (unsigned j = 0; j < m; j += 4) {
+          const uint4 w = m4[j >> 2];
+          seen |= w.x == (unsigned)q || (j + 1 < m && w.y == (unsigned)q) || (j + 2 < m && w.z == (unsigned)q) ||
+                  (j + 3 < m && w.w == (unsigned)q);
+        }
+        if (seen) return;
       }
-      if (seen) return;
       if ((unsigned)q < p0) owner = false;
       if (m == (unsigned)kClusterMax) *over = true;
       else mem[m++] = (unsigned)q;
@@ -2028,15 +2044,17 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
               rm |= 1u << (dx + H::R);
           if (!rm) continue;
           const int row = cur + dz * g.nxy + dy * g.nx;
-          for (unsigned bits = bm_span(bm, row - H::R) & rm; bits; bits &= bits - 1)
-            add(row + __builtin_ctz(bits) - H::R);
+          for (unsigned bits = bm_span(bm, row - H::R) & rm; bits; bits &= bits - 1) {
+            const int dx = __builtin_ctz(bits) - H::R;
+            add(row + dx, dx, dy, dz);
+          }
         } else {
 #pragma unroll
           for (int dx = -H::R; dx <= H::R; ++dx) {
             if (!H::read(dx, dy, dz) || (dx == 0 && dy == 0 && dz == 0)) continue;
             const bool in = ar.in(dx, dy, dz);
             const int q = in ? cur + dz * g.nxy + dy * g.nx + dx : cur;
-            if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q);
+            if (in && ((bm[q >> 6] >> (q & 63)) & 1ull)) add(q, dx, dy, dz);
           }
         }
       }
@@ -2056,8 +2074,10 @@ __device__ unsigned gather(const unsigned long long* bm, unsigned p0, const Geom
 // member requested while the current member's rows are scanned (members
 // away from the first and last rows only), so that the queue's steps do not
 // each wait a full load round trip.  Membership of a cell within a 16x16
-// window around the owner is one bit of `vis` (8 words); only cells outside
-// it are looked up in the member list.
+// window (the owner's row and the 15 below it, 8 columns either side) is one
+// bit of `vis` (8 words); only cells outside it are looked up in the member
+// list.  Members of an owner's cluster all lie at larger indices, so no row
+// above the owner's is needed.
 template <int K>
 __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const GeomD& g, unsigned* mem,
                              unsigned* vis, bool* over) {
@@ -2070,10 +2090,10 @@ __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const Ge
   const Pt oc = coords_of((int)p0, g);
 #pragma unroll
   for (int w = 0; w < 8; ++w) vis[w] = 0u;
-  vis[(8 * 16 + 8) >> 5] = 1u << ((8 * 16 + 8) & 31);  // the owner
+  vis[0] = 1u << 8;  // the owner
   // q at grid coordinates (qx, qy)
   auto add = [&](int q, int qx, int qy) {
-    const int rx = qx - oc.x + 8, ry = qy - oc.y + 8;
+    const int rx = qx - oc.x + 8, ry = qy - oc.y;
     if ((unsigned)rx < 16u && (unsigned)ry < 16u) {
       const unsigned bit = (unsigned)(ry * 16 + rx), mk = 1u << (bit & 31u);
       const unsigned w = vis[bit >> 5];
