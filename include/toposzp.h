@@ -200,9 +200,10 @@ int toposzp_compress_batch(uint32_t count, const toposzp_compress_job *h_jobs, c
                            void *d_ws, size_t ws_bytes, void *stream);
 int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job *h_jobs, void *d_ws, size_t ws_bytes,
                              void *stream);
-/* Counters (as toposzp_decompress_stats) of job `index` of the last batched
- * decompression on this workspace with these jobs. */
-int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job *h_jobs, const void *d_ws,
+/* Counters (as toposzp_decompress_stats, with the same conditions) of job
+ * `index` of the last batched decompression on this workspace with these
+ * jobs. */
+int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job *h_jobs, void *d_ws,
                                    uint32_t index, int64_t out[5], void *stream);
 
 /* Launch shapes used by every call of this process (they change no byte of
@@ -230,11 +231,14 @@ int toposzp_autotune_decompress_batch(uint32_t count, const toposzp_decompress_j
  * TOPOSZP_E_CORRUPT. */
 int toposzp_inspect(const uint8_t *h_hdr, size_t n, toposzp_info *out);
 
-/* Counters of the last decompression on this workspace (synchronises
- * `stream`): out[0] refinement rounds run, [1] saddle updates committed,
- * [2] flattened saddles queued, [3] extrema moved by the stencil,
- * [4] flattened extrema left in place by the error budget. */
-int toposzp_decompress_stats(const void *d_ws, int64_t out[5], void *stream);
+/* Counters of the last decompression on this workspace: out[0] refinement
+ * rounds run, [1] saddle updates committed, [2] flattened saddles queued,
+ * [3] extrema moved by the stencil, [4] flattened extrema left in place by
+ * the error budget.  They are gathered on request from what the
+ * decompression left in the workspace: call this on the decompression's
+ * stream before any other call uses the workspace.  Enqueues one small
+ * kernel that writes the control block of d_ws, then synchronises `stream`. */
+int toposzp_decompress_stats(void *d_ws, int64_t out[5], void *stream);
 
 /* Per-kernel timing with HIP events on the call's stream (a diagnostic for
  * one host thread and one device: the events are shared by all calls).

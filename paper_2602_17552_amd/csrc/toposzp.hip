@@ -106,6 +106,8 @@ struct Ctrl {
   unsigned hflags;            // header check of this call: 0 good, 1 corrupt, 2 capacity
   unsigned big;               // owner candidates whose cluster was too large for a workgroup
   unsigned long long stats[5];// rounds, commits, queued, stencil moves, budget skips
+  unsigned long long rp_commits;  // commits of the tail's replay of over-size clusters
+  unsigned rp_rounds;             // and its rounds
   Plan plan;
   unsigned fs_count;          // field-scope compression: flattened extrema marked
   unsigned over[kOverMax];    // the first kOverMax of those candidates
@@ -1444,6 +1446,8 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     // this call's header verdict and counters for refine/tail
     ct->hflags = h.ok == 1 ? (room ? 0u : 2u) : (h.ok == -1 ? 2u : 1u);
     ct->big = 0;
+    ct->rp_commits = 0;
+    ct->rp_rounds = 0;
     Plan& p = ct->plan;
     p.valid = room ? 1 : 0;
     if (room) {
@@ -2321,20 +2325,41 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
   }
 }
 
-// Refines the queued saddles of the chunk behind workgroup slot w_id.
+// The call's status, from the header check and the flags of the decode
+// workgroups (all finished before the refine kernel starts).
+__device__ __forceinline__ void status_body(const RefArgs& a, const Plan& pl, unsigned hf) {
+  __shared__ unsigned s_fl;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_fl = 0;
+  __syncthreads();
+  if (hf == 0 && pl.valid) {
+    const DecLayout L = dec_layout(((uint64_t)pl.g.n + kB - 1) / kB, (uint64_t)pl.nch);
+    const unsigned* df = reinterpret_cast<const unsigned*>(a.ws + L.dflag);
+    unsigned fl = 0;
+    for (int k = tid; k < pl.nch; k += (int)blockDim.x) fl |= df[k];
+    if (fl) atomicOr(&s_fl, fl);
+  }
+  __syncthreads();
+  if (tid == 0) *a.status = hf == 2u ? TOPOSZP_E_CAPACITY : (hf != 0u || s_fl) ? TOPOSZP_E_CORRUPT : TOPOSZP_OK;
+}
+
+// Refines the queued saddles of the chunk behind workgroup slot w_id; slot 0
+// also writes the call's status.
 __device__ __forceinline__ void refine_body(const RefArgs& a, int w_id, RefShared& sh) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_commits, s_rounds, s_ok;
+  __shared__ unsigned s_commits, s_rounds, s_ok, s_hf;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_p = ct->plan;
-    s_ok = ct->hflags == 0 && s_p.valid && s_p.topo;
+    s_hf = ct->hflags;
+    s_ok = s_hf == 0 && s_p.valid && s_p.topo;
     s_commits = 0;
     s_rounds = 0;
   }
   __syncthreads();
   const Plan& pl = s_p;
+  if (w_id == 0) status_body(a, pl, s_hf);
   if (!s_ok || w_id >= xcd_grid(pl.nch)) return;
   const int c = xcd_chunk(w_id, pl.nch);
   if (c >= pl.nch) return;
@@ -2374,7 +2399,7 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
 // for the refine kernel do not fit the tail's LDS; clusters already settled
 // by the refine kernel neither commit nor change here (their inputs are
 // unchanged), so only the large ones progress.  Returns the rounds run;
-// commits go to stats[1].
+// the commits go to the control block.
 template <int ND, int K>
 __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout& L) {
   __shared__ unsigned s_commits;
@@ -2431,7 +2456,7 @@ __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout
     total += commits;
     if (commits == 0) break;
   }
-  if (tid == 0) ctrl_of(a.ws)->stats[1] = total;
+  if (tid == 0) ctrl_of(a.ws)->rp_commits = total;
   return (unsigned)min(round, pl.max_rounds);
 }
 
@@ -2520,7 +2545,7 @@ __device__ unsigned gather_over(const unsigned long long* bm, const GeomD& g, co
 }
 
 // The colour-phased Jacobi schedule over the nm gathered members.  Returns
-// the rounds run; the commits go to stats[1].
+// the rounds run; the commits go to the control block.
 template <int ND, int K>
 __device__ unsigned replay_list(const RefArgs& a, const Plan& pl, TailShared& t, unsigned nm) {
   const uint8_t* labels = a.in + pl.s6_off;
@@ -2563,7 +2588,7 @@ __device__ unsigned replay_list(const RefArgs& a, const Plan& pl, TailShared& t,
     total += commits;
     if (commits == 0) break;
   }
-  if (tid == 0) ctrl_of(a.ws)->stats[1] = total;
+  if (tid == 0) ctrl_of(a.ws)->rp_commits = total;
   return (unsigned)min(round, pl.max_rounds);
 }
 
@@ -2581,71 +2606,83 @@ __device__ bool replay_over(const RefArgs& a, const Plan& pl, const DecLayout& L
   return true;
 }
 
-// Status and counters of the decompression (one workgroup), after the
-// replay of the clusters too large for the refine kernel, if any.
+// After the refine kernel (one workgroup): the replay of the clusters too
+// large for it, if there are any.
 __device__ __forceinline__ void tail_body(const RefArgs& a) {
   __shared__ Plan s_p;
-  __shared__ unsigned s_big, s_ok, s_hf, s_fl, s_rounds;
-  __shared__ unsigned long long s_sum[4];
+  __shared__ unsigned s_big;
   __shared__ TailShared s_t;
   Ctrl* ct = ctrl_of(a.ws);
+  if (threadIdx.x == 0) {
+    s_big = 0;
+    const unsigned big = ct->big;  // set only by a refine kernel that ran on a valid stream
+    if (big) {
+      s_p = ct->plan;
+      s_big = big;
+    }
+  }
+  __syncthreads();
+  if (!s_big) return;
+  const Plan& pl = s_p;
+  const DecLayout L = dec_layout(((uint64_t)pl.g.n + kB - 1) / kB, (uint64_t)pl.nch);
+  const unsigned nc = s_big;
+  unsigned trounds = 0;
+  switch (pl.ndim * 8 + pl.k) {
+    case 2 * 8 + 3:
+      if (!replay_over<2, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 3>(a, pl, L);
+      break;
+    case 2 * 8 + 5:
+      if (!replay_over<2, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 5>(a, pl, L);
+      break;
+    case 2 * 8 + 7:
+      if (!replay_over<2, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 7>(a, pl, L);
+      break;
+    case 3 * 8 + 3:
+      if (!replay_over<3, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 3>(a, pl, L);
+      break;
+    case 3 * 8 + 5:
+      if (!replay_over<3, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 5>(a, pl, L);
+      break;
+    default:
+      if (!replay_over<3, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 7>(a, pl, L);
+      break;
+  }
+  if (threadIdx.x == 0) ct->rp_rounds = trounds;
+}
+
+// The counters of the last decompression on a workspace, from the per-chunk
+// counts of the decode kernel, the refine kernel's spread lines and the
+// tail's replay (one workgroup, on request).
+__global__ __launch_bounds__(1024) void stats_kernel(uint8_t* ws) {
+  __shared__ Plan s_p;
+  __shared__ unsigned s_ok, s_rounds;
+  __shared__ unsigned long long s_sum[4];
+  Ctrl* ct = ctrl_of(ws);
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_p = ct->plan;
-    s_hf = ct->hflags;
-    s_ok = s_hf == 0 && s_p.valid;
-    s_big = ct->big;
+    s_ok = ct->hflags == 0 && s_p.valid;
     s_sum[0] = s_sum[1] = s_sum[2] = s_sum[3] = 0;
-    s_fl = 0;
     s_rounds = 0;
-    ct->stats[1] = 0;
   }
   __syncthreads();
   const Plan& pl = s_p;
   const bool ok = s_ok != 0;
-  const uint64_t nb = ok ? ((uint64_t)pl.g.n + kB - 1) / kB : 0;
-  const DecLayout L = dec_layout(nb, ok ? (uint64_t)pl.nch : 0);
-  unsigned trounds = 0;
-  if (ok && pl.topo && s_big) {
-    const unsigned nc = s_big;
-    switch (pl.ndim * 8 + pl.k) {
-      case 2 * 8 + 3:
-        if (!replay_over<2, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 3>(a, pl, L);
-        break;
-      case 2 * 8 + 5:
-        if (!replay_over<2, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 5>(a, pl, L);
-        break;
-      case 2 * 8 + 7:
-        if (!replay_over<2, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<2, 7>(a, pl, L);
-        break;
-      case 3 * 8 + 3:
-        if (!replay_over<3, 3>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 3>(a, pl, L);
-        break;
-      case 3 * 8 + 5:
-        if (!replay_over<3, 5>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 5>(a, pl, L);
-        break;
-      default:
-        if (!replay_over<3, 7>(a, pl, L, nc, s_t, &trounds)) trounds = replay_all<3, 7>(a, pl, L);
-        break;
-    }
-  }
-  __syncthreads();
   unsigned long long q = 0, mv = 0, sk = 0, cm = 0;
-  unsigned fl = 0, rd = 0;
+  unsigned rd = 0;
   if (ok) {
-    const unsigned* cnt = reinterpret_cast<const unsigned*>(a.ws + L.cnt);
-    const unsigned* mo = reinterpret_cast<const unsigned*>(a.ws + L.moves);
-    const unsigned* skp = reinterpret_cast<const unsigned*>(a.ws + L.skips);
-    const unsigned* df = reinterpret_cast<const unsigned*>(a.ws + L.dflag);
+    const DecLayout L = dec_layout(((uint64_t)pl.g.n + kB - 1) / kB, (uint64_t)pl.nch);
+    const unsigned* cnt = reinterpret_cast<const unsigned*>(ws + L.cnt);
+    const unsigned* mo = reinterpret_cast<const unsigned*>(ws + L.moves);
+    const unsigned* skp = reinterpret_cast<const unsigned*>(ws + L.skips);
     for (int k = tid; k < pl.nch; k += blockDim.x) {
       q += cnt[k];
       mv += mo[k];
       sk += skp[k];
-      fl |= df[k];
     }
   }
   if (tid < kSpreadLines) {
-    const Spread* sp = spread_of(a.ws) + tid;
+    const Spread* sp = spread_of(ws) + tid;
     cm = sp->commits;
     rd = sp->rounds;
   }
@@ -2655,7 +2692,6 @@ __device__ __forceinline__ void tail_body(const RefArgs& a) {
     mv += __shfl_xor(mv, o);
     sk += __shfl_xor(sk, o);
     cm += __shfl_xor(cm, o);
-    fl |= (unsigned)__shfl_xor((int)fl, o);
     rd = max(rd, (unsigned)__shfl_xor((int)rd, o));
   }
   if ((tid & 63) == 0) {
@@ -2663,23 +2699,18 @@ __device__ __forceinline__ void tail_body(const RefArgs& a) {
     atomicAdd(&s_sum[1], mv);
     atomicAdd(&s_sum[2], sk);
     atomicAdd(&s_sum[3], cm);
-    if (fl) atomicOr(&s_fl, fl);
     if (rd) atomicMax(&s_rounds, rd);
   }
   __syncthreads();
   if (tid == 0) {
-    const unsigned long long commits = ct->stats[1] + s_sum[3];
-    unsigned rounds = max(trounds, s_rounds);
-    if (ok && pl.topo && rounds == 0) rounds = 1;  // a round that found nothing to do
-    ct->stats[0] = ok && pl.topo ? rounds : 0;
-    ct->stats[1] = commits;
+    const bool topo = ok && pl.topo;
+    unsigned rounds = max(ct->rp_rounds, s_rounds);
+    if (topo && rounds == 0) rounds = 1;  // a round that found nothing to do
+    ct->stats[0] = topo ? rounds : 0;
+    ct->stats[1] = ct->rp_commits + s_sum[3];
     ct->stats[2] = s_sum[0];
     ct->stats[3] = s_sum[1];
     ct->stats[4] = s_sum[2];
-    int status = TOPOSZP_OK;
-    if (s_hf == 2u) status = TOPOSZP_E_CAPACITY;
-    else if (s_hf != 0u || s_fl) status = TOPOSZP_E_CORRUPT;
-    *a.status = status;
   }
 }
 
@@ -3485,13 +3516,13 @@ int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job* h_job
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
-int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job* h_jobs, const void* d_ws,
+int toposzp_decompress_batch_stats(uint32_t count, const toposzp_decompress_job* h_jobs, void* d_ws,
                                    uint32_t index, int64_t out[5], void* stream) {
   if (count < 1 || count > (uint32_t)kBatchMax || !h_jobs || !d_ws || index >= count || !out)
     return TOPOSZP_E_INVALID_ARG;
   std::vector<size_t> offs(count);
   if (dec_batch_layout(count, h_jobs, offs.data()) == 0) return TOPOSZP_E_INVALID_ARG;
-  return toposzp_decompress_stats((const uint8_t*)d_ws + offs[index], out, stream);
+  return toposzp_decompress_stats((uint8_t*)d_ws + offs[index], out, stream);
 }
 
 int toposzp_set_tuning(const toposzp_tuning* t) {
@@ -3601,11 +3632,13 @@ int toposzp_inspect(const uint8_t* h, size_t n, toposzp_info* out) {
   return TOPOSZP_OK;
 }
 
-int toposzp_decompress_stats(const void* d_ws, int64_t out[5], void* stream) {
-  if (!d_ws || !out) return TOPOSZP_E_INVALID_ARG;
+int toposzp_decompress_stats(void* d_ws, int64_t out[5], void* stream) {
+  if (!d_ws || !out || ((uintptr_t)d_ws & 255)) return TOPOSZP_E_INVALID_ARG;
   const Ctrl* ct = (const Ctrl*)d_ws;
   unsigned long long st[5];
-  if (hipMemcpyAsync(st, (const void*)ct->stats, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, (uint8_t*)d_ws);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(st, (const void*)ct->stats, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
           hipSuccess ||
       hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
     return TOPOSZP_E_DEVICE;
