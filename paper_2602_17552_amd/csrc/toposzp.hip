@@ -1120,7 +1120,7 @@ __device__ void put8(uint8_t* h, int off, uint64_t v) { memcpy(h + off, &v, 8); 
 __device__ void put4(uint8_t* h, int off, uint32_t v) { memcpy(h + off, &v, 4); }
 __device__ void put2(uint8_t* h, int off, uint16_t v) { memcpy(h + off, &v, 2); }
 
-// Places chunk c's staged planes; the last chunk also writes the header.
+// Places chunk c's staged planes; chunk 0 also writes the header.
 __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   __shared__ uint8_t hdr[kHdr];
   __shared__ uint64_t s_seg[2 * kNSeg];
@@ -1131,7 +1131,9 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   __shared__ double s_eps;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const bool last = c == a.nch - 1;  // writes the header
+  // the first chunk's workgroup (dispatched first) also writes the header,
+  // so that its longer chain overlaps the other chunks' copies
+  const bool head = c == 0;
   const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
   const unsigned* td = reinterpret_cast<const unsigned*>(a.ws + L.tot_d);
   const unsigned* tr = reinterpret_cast<const unsigned*>(a.ws + L.tot_r);
@@ -1140,7 +1142,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   if (a.fused) {
     // td/tr hold per-chunk plane counts: every workgroup sums its
     // predecessors' (its offsets) and everybody's (the rank planes follow
-    // all data planes); the last one also gathers the flags
+    // all data planes); the header's workgroup also gathers the flags
     // (four chunks per 16-byte load; the arrays are padded to 16 bytes)
     unsigned pd = 0, pr = 0, ad = 0, ar = 0, fl = 0;
     const uint4* td4 = reinterpret_cast<const uint4*>(td);
@@ -1149,7 +1151,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     const int n4 = (a.nch + 3) >> 2;
     for (int j4 = tid; j4 < n4; j4 += 256) {
       const uint4 vd = td4[j4], vr = tr4[j4];
-      const uint4 vf = last ? cf4[j4] : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 vf = head ? cf4[j4] : make_uint4(0u, 0u, 0u, 0u);
       const unsigned d[4] = {vd.x, vd.y, vd.z, vd.w}, r[4] = {vr.x, vr.y, vr.z, vr.w};
       const unsigned f[4] = {vf.x, vf.y, vf.z, vf.w};
 #pragma unroll
@@ -1178,7 +1180,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
       s_red[3][wv] = ar;
       s_red[4][wv] = fl;
     }
-    if (last) {
+    if (head) {
       __shared__ RangeSh s_rs;
       float e, vmin, vmax;
       double eps;
@@ -1199,7 +1201,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     totr = (uint64_t)s_red[3][0] + s_red[3][1] + s_red[3][2] + s_red[3][3];
     nd = td[c];
     nr = tr[c];
-    if (last && tid == 0) s_flags |= s_red[4][0] | s_red[4][1] | s_red[4][2] | s_red[4][3];
+    if (head && tid == 0) s_flags |= s_red[4][0] | s_red[4][1] | s_red[4][2] | s_red[4][3];
   } else {
     // td/tr hold exclusive prefixes, the control block the totals
     totd = ct->tot_data;
@@ -1208,7 +1210,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
     nd = (c + 1 < a.nch ? (uint64_t)td[c + 1] : totd) - b0;
     r0 = tr[c];
     nr = (c + 1 < a.nch ? (uint64_t)tr[c + 1] : totr) - r0;
-    if (last && tid == 0) {
+    if (head && tid == 0) {
       s_flags = ct->cflags;
       s_e = ct->e;
       s_vmin = ct->vmin;
@@ -1230,7 +1232,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
       if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * r0;
     }
   }
-  if (!last) return;
+  if (!head) return;
   __syncthreads();
 
   const unsigned flags = s_flags;
@@ -2606,8 +2608,8 @@ __device__ bool replay_over(const RefArgs& a, const Plan& pl, const DecLayout& L
   return true;
 }
 
-// After the refine kernel (one workgroup): the replay of the clusters too
-// large for it, if there are any.
+// After the refine kernel (one workgroup of 256 threads): the replay of the
+// clusters too large for it, if there are any.
 __device__ __forceinline__ void tail_body(const RefArgs& a) {
   __shared__ Plan s_p;
   __shared__ unsigned s_big;
@@ -2714,7 +2716,7 @@ __global__ __launch_bounds__(1024) void stats_kernel(uint8_t* ws) {
   }
 }
 
-__global__ __launch_bounds__(1024) void tail_kernel(RefArgs a) { tail_body(a); }
+__global__ __launch_bounds__(256) void tail_kernel(RefArgs a) { tail_body(a); }
 
 // ---------------------------------------------------------------------------
 // Topological errors of a reconstruction (Section III-B): per point, the
@@ -2898,7 +2900,7 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
   });
 }
 
-__global__ __launch_bounds__(1024) void tail_batch_kernel(const uint8_t* __restrict__ tab) {
+__global__ __launch_bounds__(256) void tail_batch_kernel(const uint8_t* __restrict__ tab) {
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
   for_items(h->count, [&](int f) { tail_body(jobs[f].ref); });
@@ -3380,7 +3382,7 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
   ev_end(3, s);
   ev_begin(4, s);
   hipLaunchKernelGGL(refine_kernel, dim3(slots), dim3(kRefThreads), 0, s, J.ref);
-  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(1024), 0, s, J.ref);
+  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(256), 0, s, J.ref);
   ev_end(4, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
@@ -3512,7 +3514,7 @@ int toposzp_decompress_batch(uint32_t count, const toposzp_decompress_job* h_job
   else
     hipLaunchKernelGGL(decode_batch_kernel<4>, dim3(batch_grid((int)ns, wpc)), dim3(256), 0, s, ws);
   hipLaunchKernelGGL(refine_batch_kernel, dim3(batch_grid((int)ns, 2 * wpc)), dim3(kRefThreads), 0, s, ws);
-  hipLaunchKernelGGL(tail_batch_kernel, dim3(batch_grid((int)count, 1)), dim3(1024), 0, s, ws);
+  hipLaunchKernelGGL(tail_batch_kernel, dim3(batch_grid((int)count, 1)), dim3(256), 0, s, ws);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
