@@ -303,3 +303,27 @@ def test_parity_full_size(tsz, ora, name, gen, eb):
     ev = ora.eval_topology(f, rec)
     print(name, "bytes", s.size, "ratio %.2f" % (f.nbytes / s.size), ev, stats, flush=True)
     assert ev["FP"] == 0 and ev["FT"] == 0
+
+
+def test_stats_follow_last_decompression(tsz, ora):
+    # the counters are gathered on request from what the last decompression
+    # left in the workspace: asking twice gives the same numbers, and a later
+    # decompression on the same workspace replaces them
+    import torch
+    shape = (130, 150)
+    ws = tsz.Workspace(shape)
+    cases = [(datagen.gaussian_bumps_2d(*shape, 12, seed=9), 2e-2, {}),
+             (datagen.noise(shape, seed=4), 0.3, {}),
+             (datagen.noise(shape, seed=5), 0.3, {"topo": False})]
+    for f, eb, params in cases:
+        rc, s_o = ora.compress(f, eb, "abs", **params)
+        assert rc == 0
+        st, rec = tsz.decompress(torch.from_numpy(s_o).cuda(), shape, ws=ws)
+        assert st == tsz.OK
+        first = tsz.decompress_stats(ws)
+        again = tsz.decompress_stats(ws)
+        _, rec_o, stats_o = ora.decompress(s_o, shape)
+        assert np.array_equal(rec.cpu().numpy().view(np.uint32), rec_o.view(np.uint32))
+        assert first == again
+        for k in ("rounds", "commits", "stencil_moves", "budget_skips"):
+            assert first[k] == stats_o[k], (k, first, stats_o)
