@@ -84,7 +84,47 @@ def cpu_baseline(field, eb, target_s=10.0):
         "sample": "%d whole-field round trips (compress + decompress) of the workload; "
                   "compress %.4f GB/s, decompress %.4f GB/s" % (reps, nbytes * reps / tc / 1e9,
                                                                   nbytes * reps / td / 1e9),
+        "host": host_cpu(),
+        "all_cores": cpu_all_cores(field, eb, s, rec),
     }, s, rec
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0))}
+
+
+def cpu_all_cores(field, eb, s_ref, rec_ref, max_threads=16):
+    """The same single-threaded oracle, one whole-field round trip per thread
+    on up to max_threads threads at once (its C calls release the GIL, and the
+    block-scope path shares no state): aggregate field bytes per wall second.
+    Every thread's stream and reconstruction must equal the single run's."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    from oracle import oracle as ora
+    nt = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+
+    def one(_):
+        rc, s = ora.compress(field, eb, "rel")
+        rc2, rec, _ = ora.decompress(s, field.shape)
+        return rc == 0 and rc2 == 0 and np.array_equal(s, s_ref) and \
+            np.array_equal(rec.view(np.uint32), rec_ref.view(np.uint32))
+
+    with ThreadPoolExecutor(nt) as ex:
+        t0 = time.perf_counter()
+        same = list(ex.map(one, range(nt)))
+        wall = time.perf_counter() - t0
+    return {"value": round(field.nbytes * nt / wall / 1e9, 4), "unit": "GB/s", "threads": nt,
+            "sample": "%d concurrent whole-field round trips, %.2f s wall" % (nt, wall),
+            "identical": all(same)}
 
 
 def batch_leg(tsz, torch, dev, reps=20):
