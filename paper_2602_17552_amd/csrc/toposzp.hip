@@ -1767,19 +1767,30 @@ __device__ __forceinline__ unsigned bm_span(const unsigned long long* bm, int lo
   return (unsigned)(sh ? (w[0] >> sh) | (w[1] << (64 - sh)) : w[0]);
 }
 
-// One evaluation of the queued saddle p on the current field: 0 reject,
-// 1 already a saddle, 2 accept (value in *vout).  The cells the
-// classifications read (L1 distance <= 2) are loaded in one batch and kept in
-// registers (addresses outside the grid are replaced by p's own); window
-// cells beyond them are read as the sum reaches them.
+// The core of an evaluation of p: the values at L1 distance <= 2 (all that
+// the classifications read; entries for cells outside the grid hold values
+// that are never used) and the labels of p's face neighbours.
+template <int ND>
+struct Core {
+  static constexpr int CZ = ND == 3 ? 2 : 0;
+  float v[2 * CZ + 1][5][5];  // [dz + CZ][dy + 2][dx + 2], entries with L1 <= 2
+  int lab[6];
+};
+
+// The read set of an evaluation lies inside its core when the Gaussian
+// window does (radius 1, or radius 2 in 2D): such an evaluation needs no
+// memory once the core is known.  The replay keeps cores in registers in 2D
+// only (13 values); the 25 of a 3D core would spill.
 template <int ND, int K>
-__device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels, int p, Pt c,
-                                        const Plan& pl, float* vout) {
-  using H = Hood<ND, K>;
-  constexpr int r = H::r, CZ = ND == 3 ? 2 : 0;  // core: L1 <= 2, box half-width 2
-  const GeomD& g = pl.g;
+constexpr bool kCoreOnly = ND == 2 && K / 2 <= 2;
+
+// Loads the core of p (one batch of loads).
+template <int ND, int K>
+__device__ __forceinline__ void load_core(const float* fld, const uint8_t* labels, int p, Pt c, const GeomD& g,
+                                          Core<ND>& C) {
+  constexpr int CZ = Core<ND>::CZ;
   const Around<ND, K> ar(c, g);
-  float v[2 * CZ + 1][5][5];
+  auto& v = C.v;
   if (far_from_ends<ND>(p, g)) {
     // one vector load per row of the core (every span lies inside the
     // array); rows outside the grid read p's own row instead
@@ -1805,13 +1816,43 @@ __device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels,
         }
   }
   constexpr int U[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
-  int lab[6];
 #pragma unroll
   for (int j = 0; j < 2 * ND; ++j) {
     const bool ex = ar.in(U[j][0], U[j][1], U[j][2]);
     const int q = ex ? p + U[j][2] * g.nxy + U[j][1] * g.nx + U[j][0] : p;
-    lab[j] = (labels[q >> 2] >> (2 * (q & 3))) & 3;
+    C.lab[j] = (labels[q >> 2] >> (2 * (q & 3))) & 3;
   }
+}
+
+// Sets the core entry at offset (dx, dy, dz) (L1 <= 2) to x: unrolled
+// selects, so that the core stays in registers.
+template <int ND>
+__device__ __forceinline__ void core_set(Core<ND>& C, int dx, int dy, int dz, float x) {
+  constexpr int CZ = Core<ND>::CZ;
+#pragma unroll
+  for (int oz = -CZ; oz <= CZ; ++oz)
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy)
+#pragma unroll
+      for (int ox = -2; ox <= 2; ++ox) {
+        if ((ox < 0 ? -ox : ox) + (oy < 0 ? -oy : oy) + (oz < 0 ? -oz : oz) > 2) continue;
+        if (dx == ox && dy == oy && dz == oz) C.v[oz + CZ][oy + 2][ox + 2] = x;
+      }
+}
+
+// One evaluation of the queued saddle p from its core: 0 reject, 1 already a
+// saddle, 2 accept (value in *vout).  Window cells beyond the core are read
+// from fld as the sum reaches them.
+template <int ND, int K>
+__device__ __forceinline__ int eval_core(const float* fld, const Core<ND>& C, int p, Pt c, const Plan& pl,
+                                         float* vout) {
+  using H = Hood<ND, K>;
+  constexpr int r = H::r, CZ = Core<ND>::CZ;
+  const GeomD& g = pl.g;
+  const Around<ND, K> ar(c, g);
+  const auto& v = C.v;
+  const int* lab = C.lab;
+  constexpr int U[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
   const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
   // class of the cell at offset o (L1 <= 1) with p's value taken as pv
   auto cls = [&](int ox, int oy, int oz, float pv) -> int {
@@ -1898,6 +1939,16 @@ __device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels,
   return 2;
 }
 
+// One evaluation of the queued saddle p on the current field (as eval_core,
+// after loading the core).
+template <int ND, int K>
+__device__ __forceinline__ int evaluate(const float* fld, const uint8_t* labels, int p, Pt c,
+                                        const Plan& pl, float* vout) {
+  Core<ND> C;
+  load_core<ND, K>(fld, labels, p, c, pl.g, C);
+  return eval_core<ND, K>(fld, C, p, c, pl, vout);
+}
+
 __device__ __forceinline__ int colour_of(Pt c, int ndim) {
   return ndim == 3 ? (int)(((unsigned)c.x + 2u * (unsigned)c.y + 3u * (unsigned)c.z) % 7u)
                    : (int)(((unsigned)c.x + 2u * (unsigned)c.y) % 5u);
@@ -1981,6 +2032,7 @@ struct RefShared {
   unsigned cflag[kBatch];           // bit0 still running, bit1 committed this round
   unsigned crounds[kBatch];
   unsigned cpts[kRefThreads];       // points committed in the current phase
+  float cval[kRefThreads];          // and their new values
   unsigned nc, ncp, any;
 };
 
@@ -2269,6 +2321,18 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
         const Pt myc = coords_of(my, g);
         const int col = colour_of(myc, ND);
         bool settled = !act;
+        // when the read set lies inside the core, each member keeps its core
+        // in registers for the whole pack, loaded once and updated from the
+        // commit lists: its evaluations then read no memory
+        constexpr bool CO = kCoreOnly<ND, K>;
+        Core<ND> C;
+        if constexpr (CO) {
+          if (act) load_core<ND, K>(a.out, labels, my, myc, g, C);
+        }
+        auto eval = [&](float* vv) {
+          if constexpr (CO) return eval_core<ND, K>(a.out, C, my, myc, pl, vv);
+          else return evaluate<ND, K>(a.out, labels, my, myc, pl, vv);
+        };
         int round = 1;
         for (; round <= cap; ++round) {
           // every unsettled member is evaluated on the field as the round
@@ -2278,19 +2342,24 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
           const bool live = act && (sh.cflag[cl] & 1u);
           int res = 0;
           float v = 0.0f;
-          if (live && !settled) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
+          if (live && !settled) res = eval(&v);
           bool dirty = false;
           for (int ph = 0; ph < pl.ncol; ++ph) {
             const bool mine = live && !settled && col == ph;
-            if (__syncthreads_or(mine && dirty)) {
-              if (mine && dirty) res = evaluate<ND, K>(a.out, labels, my, myc, pl, &v);
+            if constexpr (CO) {
+              // the core changes only between phases: no reader to wait for
+              if (mine && dirty) res = eval(&v);
+            } else if (__syncthreads_or(mine && dirty)) {
+              if (mine && dirty) res = eval(&v);
               __syncthreads();  // Jacobi: every evaluation of the phase reads before any commit
             }
             const bool commit = mine && res == 2;
             if (mine && res != 0) settled = true;
             if (commit) {
               a.out[my] = v;
-              sh.cpts[atomicAdd(&sh.ncp, 1u)] = (unsigned)my;
+              const unsigned k = atomicAdd(&sh.ncp, 1u);
+              sh.cpts[k] = (unsigned)my;
+              sh.cval[k] = v;
               atomicOr(&sh.cflag[cl], 2u);
               ++commits;
             }
@@ -2299,7 +2368,12 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
             const unsigned ncp = sh.ncp;
             for (unsigned j = 0; j < ncp; ++j) {
               const Pt ck = coords_of((int)sh.cpts[j], g);
-              dirty |= H::reads(ck.x - myc.x, ck.y - myc.y, ck.z - myc.z);
+              const int dx = ck.x - myc.x, dy = ck.y - myc.y, dz = ck.z - myc.z;
+              dirty |= H::reads(dx, dy, dz);
+              if constexpr (CO) {
+                if (act && (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz) <= 2)
+                  core_set<ND>(C, dx, dy, dz, sh.cval[j]);
+              }
             }
             __syncthreads();
             if (tid == 0) sh.ncp = 0;
