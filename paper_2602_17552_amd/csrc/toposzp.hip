@@ -2031,9 +2031,10 @@ struct RefShared {
   unsigned off[kBatch + 1];         // first lane of each cluster in the pack
   unsigned cflag[kBatch];           // bit0 still running, bit1 committed this round
   unsigned crounds[kBatch];
-  unsigned cpts[kRefThreads];       // points committed in the current phase
+  unsigned cpts[kRefThreads];       // ring of committed points (entry k at k mod kRefThreads)
   float cval[kRefThreads];          // and their new values
-  unsigned nc, ncp, any;
+  unsigned ncp;                     // commits of the pack so far
+  unsigned nc, any;
 };
 
 // Gathers the cluster of owner candidate p0 (lane-serial): every queued
@@ -2333,6 +2334,7 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
           if constexpr (CO) return eval_core<ND, K>(a.out, C, my, myc, pl, vv);
           else return evaluate<ND, K>(a.out, labels, my, myc, pl, vv);
         };
+        unsigned seen = 0;  // commits of the pack already scanned
         int round = 1;
         for (; round <= cap; ++round) {
           // every unsettled member is evaluated on the field as the round
@@ -2355,9 +2357,14 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
             }
             const bool commit = mine && res == 2;
             if (mine && res != 0) settled = true;
+            // commits append to a ring and the count only grows, so nothing
+            // is reset between phases (with register cores no barrier
+            // separates a reset from the next phase's commits); a phase's
+            // commits come after the barrier that ends the previous phase's
+            // scans, and a phase holds at most kRefThreads of them
             if (commit) {
               a.out[my] = v;
-              const unsigned k = atomicAdd(&sh.ncp, 1u);
+              const unsigned k = atomicAdd(&sh.ncp, 1u) % (unsigned)kRefThreads;
               sh.cpts[k] = (unsigned)my;
               sh.cval[k] = v;
               atomicOr(&sh.cflag[cl], 2u);
@@ -2365,8 +2372,9 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
             }
             __threadfence_block();
             __syncthreads();
-            const unsigned ncp = sh.ncp;
-            for (unsigned j = 0; j < ncp; ++j) {
+            const unsigned upto = sh.ncp;  // no commit until every thread has passed the next barrier
+            for (; seen != upto; ++seen) {
+              const unsigned j = seen % (unsigned)kRefThreads;
               const Pt ck = coords_of((int)sh.cpts[j], g);
               const int dx = ck.x - myc.x, dy = ck.y - myc.y, dz = ck.z - myc.z;
               dirty |= H::reads(dx, dy, dz);
@@ -2376,7 +2384,6 @@ __device__ void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared&
               }
             }
             __syncthreads();
-            if (tid == 0) sh.ncp = 0;
           }
           // a cluster stops at its first round without a commit
           __syncthreads();
