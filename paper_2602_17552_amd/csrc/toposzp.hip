@@ -22,11 +22,13 @@
 //                    Queued saddles that cannot influence each other's
 //                    evaluation evolve independently under the colour-phased
 //                    schedule, so an isolated saddle is settled by a single
-//                    evaluation and a small cluster by one thread replaying
-//                    the schedule on its members.
-//   tail_kernel      one workgroup: the same schedule with workgroup
-//                    barriers for the rare clusters too large for one
-//                    thread; status and counters.
+//                    evaluation, and a cluster (gathered by one lane) is
+//                    replayed by the workgroup, one member per lane.  The
+//                    first workgroup also writes the call's status.
+//   tail_kernel      one workgroup: the same schedule for the rare clusters
+//                    of more than 64 members, gathered and replayed from
+//                    LDS (the whole field's queue when they do not fit).
+//   stats_kernel     one workgroup, on request: the decompression's counters.
 //
 // No kernel contends on a single global address; every device wait is
 // bounded.  Readings of points the paper leaves open are stated where used.
