@@ -146,7 +146,7 @@ __host__ __device__ inline CompLayout comp_layout(uint64_t nch, int field = 0) {
 }
 
 struct DecLayout {
-  uint64_t cnt, moves, skips, dflag, bitmap, idx, state, pend, end;
+  uint64_t cnt, moves, skips, dflag, bitmap, capped, idx, state, pend, end;
 };
 __host__ __device__ inline DecLayout dec_layout(uint64_t nb, uint64_t nch) {
   DecLayout L;
@@ -156,7 +156,8 @@ __host__ __device__ inline DecLayout dec_layout(uint64_t nb, uint64_t nch) {
   L.skips = L.moves + 4 * nch;
   L.dflag = L.skips + 4 * nch;
   L.bitmap = al256(L.dflag + 4 * nch);
-  L.idx = al256(L.bitmap + 8 * nb);
+  L.capped = al256(L.bitmap + 8 * nb);  // members of clusters stopped by the round cap
+  L.idx = al256(L.capped + 8 * nb);
   L.state = al256(L.idx + 4 * slots);
   L.pend = al256(L.state + slots);
   L.end = al256(L.pend + 4 * slots);
@@ -1571,7 +1572,10 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
       reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = 0;
       reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = 0;
     }
-    if (tid < kB && (uint64_t)c * kB + tid < h.nb) bitmap[(uint64_t)c * kB + tid] = 0;
+    if (tid < kB && (uint64_t)c * kB + tid < h.nb) {
+      bitmap[(uint64_t)c * kB + tid] = 0;
+      reinterpret_cast<unsigned long long*>(a.ws + L.capped)[(uint64_t)c * kB + tid] = 0;
+    }
     return;
   }
 
@@ -1683,8 +1687,12 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     if (cb) atomicOr(&s_corrupt, 1u);
   }
   __syncthreads();
-  // the chunk's queued-saddle bitmap and counters
-  if (tid < kB && (uint64_t)c * kB + tid < h.nb) bitmap[(uint64_t)c * kB + tid] = topo ? s_bm[tid] : 0ull;
+  // the chunk's queued-saddle bitmap (and a cleared word of the capped
+  // bitmap beside each), and counters
+  if (tid < kB && (uint64_t)c * kB + tid < h.nb) {
+    bitmap[(uint64_t)c * kB + tid] = topo ? s_bm[tid] : 0ull;
+    reinterpret_cast<unsigned long long*>(a.ws + L.capped)[(uint64_t)c * kB + tid] = 0;
+  }
   if (tid == 0) {
     reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = s_qn;
     reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = s_moves;
@@ -2405,6 +2413,10 @@ __device__ __attribute__((always_inline)) void refine_chunk(const RefArgs& a, co
         }
         if ((unsigned)tid < k1 - k0 && sh.msize[k0 + tid])
           rounds = max(rounds, (sh.cflag[tid] & 1u) ? (unsigned)cap : sh.crounds[tid]);
+        // a cluster still committing when the round cap stopped it is not
+        // settled: the whole-field replay must leave its members alone
+        if (act && (sh.cflag[cl] & 1u))
+          atomicOr(reinterpret_cast<unsigned long long*>(a.ws + L.capped) + (my >> 6), 1ull << (my & 63));
         __syncthreads();
         k0 = k1;
       }
@@ -2484,10 +2496,11 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
 
 // Whole-field replay of the schedule over every queued saddle, by one
 // workgroup with workgroup barriers.  Runs only when the clusters too large
-// for the refine kernel do not fit the tail's LDS; clusters already settled
-// by the refine kernel neither commit nor change here (their inputs are
-// unchanged), so only the large ones progress.  Returns the rounds run;
-// the commits go to the control block.
+// for the refine kernel do not fit the tail's LDS.  Clusters the refine
+// kernel settled neither commit nor change here (their inputs are
+// unchanged), and those it stopped at the round cap start settled, so only
+// the large ones progress.  Returns the rounds run; the commits go to the
+// control block.
 template <int ND, int K>
 __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout& L) {
   __shared__ unsigned s_commits;
@@ -2496,9 +2509,15 @@ __device__ unsigned replay_all(const RefArgs& a, const Plan& pl, const DecLayout
   uint8_t* state = a.ws + L.state;
   float* pend = reinterpret_cast<float*>(a.ws + L.pend);
   const uint8_t* labels = a.in + pl.s6_off;
+  const unsigned long long* capped = reinterpret_cast<const unsigned long long*>(a.ws + L.capped);
   const unsigned tid = threadIdx.x, nthr = blockDim.x;
+  // members of clusters that the refine kernel replayed up to the round cap
+  // start settled: more rounds would take them past the cap
   for (int c = 0; c < pl.nch; ++c)
-    for (unsigned t = tid; t < min(cnt[c], (unsigned)kChunk); t += nthr) state[(size_t)c * kChunk + t] = 0;
+    for (unsigned t = tid; t < min(cnt[c], (unsigned)kChunk); t += nthr) {
+      const unsigned p = idx[(size_t)c * kChunk + t];
+      state[(size_t)c * kChunk + t] = (uint8_t)((capped[p >> 6] >> (p & 63)) & 1ull);
+    }
   __syncthreads();
   int round = 1;
   unsigned long long total = 0;

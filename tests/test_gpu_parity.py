@@ -155,6 +155,12 @@ def test_parity_whole_field_replay(tsz, ora):
     # refine kernel records
     res = check(tsz, ora, "patches150", _checker_patches(7, (5, 5, 6)), 1.0, "abs")
     assert res[2]["worklist0"] > 150 * 65
+    # with one round allowed: the clusters the refine kernel stopped at the
+    # cap must not get more rounds from the whole-field replay
+    check(tsz, ora, "checker_cap1", datagen.checker_2d(145, 167, seed=309451577), 1.43446, "abs", max_rounds=1)
+    check(tsz, ora, "checker_cap1_field", datagen.checker_2d(785, 286, seed=450909876), 1.51062, "abs",
+          rank_scope=1, rbf_policy=1, max_rounds=1)
+    check(tsz, ora, "checker3d_big_cap2", datagen.checker_3d(24, 26, 28, seed=1), 1.0, "abs", max_rounds=2)
 
 
 def _all_lost(shape, seed):
