@@ -467,6 +467,8 @@ struct RefArgs {
   float* out;
   uint8_t* ws;
   int32_t* status;
+  int slots;  // workgroups per sub-slice (chunk slots of the launch)
+  int split;  // sub-slices each chunk's queue is divided into
 };
 
 __device__ __forceinline__ Ctrl* ctrl_of(uint8_t* ws) { return reinterpret_cast<Ctrl*>(ws); }
@@ -2251,23 +2253,32 @@ __device__ unsigned gather2d(const unsigned long long* bm, unsigned p0, const Ge
 // Inlined into each kernel for every (dimension, kernel size): as calls, the
 // larger instantiations paid the call convention's register saves and spills
 // (2D k = 7 refinement 15% slower, 3D 5-9%).
-template <int ND, int K>
-__device__ __attribute__((always_inline)) void refine_chunk(const RefArgs& a, const Plan& pl, int c, RefShared& sh,
-                                                            unsigned& commits, unsigned& rounds) {
+template <int ND, int K, bool SPLIT>
+__device__ __attribute__((always_inline)) void refine_chunk(const RefArgs& a, const Plan& pl, int c, int sub,
+                                                            RefShared& sh, unsigned& commits, unsigned& rounds) {
   using H = Hood<ND, K>;
   const int tid = threadIdx.x;
   const uint64_t nb = ((uint64_t)pl.g.n + kB - 1) / kB;
   const DecLayout L = dec_layout(nb, (uint64_t)pl.nch);
   const unsigned cnt0 = reinterpret_cast<const unsigned*>(a.ws + L.cnt)[c];
-  const unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
+  unsigned cnt = cnt0 < (unsigned)kChunk ? cnt0 : (unsigned)kChunk;
   const unsigned* idx = reinterpret_cast<const unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
+  if constexpr (SPLIT) {
+    // this workgroup's share of the chunk's queue: a cluster is refined by
+    // the workgroup holding its owner's entry, so any division gives the
+    // same result
+    const unsigned lo = cnt * (unsigned)sub / (unsigned)a.split;  // cnt <= 4096, split <= 8
+    cnt = cnt * (unsigned)(sub + 1) / (unsigned)a.split - lo;
+    idx += lo;
+  }
   const unsigned long long* bm = reinterpret_cast<const unsigned long long*>(a.ws + L.bitmap);
   const uint8_t* labels = a.in + pl.s6_off;
   const GeomD& g = pl.g;
   const int cap = pl.max_rounds;
 
-  // the first entry of this thread, read beside the count (the chunk's
-  // kChunk queue slots always exist; an entry past the count is not used)
+  // the first entry of this thread, read beside the count (entries past the
+  // count, at most 127 past the chunk's slots, lie inside the workspace and
+  // are not used)
   const unsigned first = idx[tid];
   for (unsigned base = 0; base < cnt; base += kCandMax) {
     // phase A, one lane per queued saddle: isolated saddles are settled by
@@ -2443,8 +2454,9 @@ __device__ __forceinline__ void status_body(const RefArgs& a, const Plan& pl, un
   if (tid == 0) *a.status = hf == 2u ? TOPOSZP_E_CAPACITY : (hf != 0u || s_fl) ? TOPOSZP_E_CORRUPT : TOPOSZP_OK;
 }
 
-// Refines the queued saddles of the chunk behind workgroup slot w_id; slot 0
-// also writes the call's status.
+// Refines the queued saddles of the chunk behind workgroup slot w_id (with
+// SPLIT, its share of them); slot 0 also writes the call's status.
+template <bool SPLIT>
 __device__ __forceinline__ void refine_body(const RefArgs& a, int w_id, RefShared& sh) {
   __shared__ Plan s_p;
   __shared__ unsigned s_commits, s_rounds, s_ok, s_hf;
@@ -2460,17 +2472,20 @@ __device__ __forceinline__ void refine_body(const RefArgs& a, int w_id, RefShare
   __syncthreads();
   const Plan& pl = s_p;
   if (w_id == 0) status_body(a, pl, s_hf);
-  if (!s_ok || w_id >= xcd_grid(pl.nch)) return;
-  const int c = xcd_chunk(w_id, pl.nch);
+  // slot-major sub-slices: workgroups `slots` apart share a chunk (and, the
+  // slot count being a multiple of 8, an XCD)
+  const int sub = SPLIT ? w_id / a.slots : 0, cs = SPLIT ? w_id - sub * a.slots : w_id;
+  if (!s_ok || cs >= xcd_grid(pl.nch)) return;
+  const int c = xcd_chunk(cs, pl.nch);
   if (c >= pl.nch) return;
   unsigned commits = 0, rounds = 0;
   switch (pl.ndim * 8 + pl.k) {
-    case 2 * 8 + 3: refine_chunk<2, 3>(a, pl, c, sh, commits, rounds); break;
-    case 2 * 8 + 5: refine_chunk<2, 5>(a, pl, c, sh, commits, rounds); break;
-    case 2 * 8 + 7: refine_chunk<2, 7>(a, pl, c, sh, commits, rounds); break;
-    case 3 * 8 + 3: refine_chunk<3, 3>(a, pl, c, sh, commits, rounds); break;
-    case 3 * 8 + 5: refine_chunk<3, 5>(a, pl, c, sh, commits, rounds); break;
-    default: refine_chunk<3, 7>(a, pl, c, sh, commits, rounds); break;
+    case 2 * 8 + 3: refine_chunk<2, 3, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
+    case 2 * 8 + 5: refine_chunk<2, 5, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
+    case 2 * 8 + 7: refine_chunk<2, 7, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
+    case 3 * 8 + 3: refine_chunk<3, 3, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
+    case 3 * 8 + 5: refine_chunk<3, 5, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
+    default: refine_chunk<3, 7, SPLIT>(a, pl, c, sub, sh, commits, rounds); break;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -2491,7 +2506,14 @@ __device__ __forceinline__ void refine_body(const RefArgs& a, int w_id, RefShare
 
 __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_kernel(RefArgs a) {
   __shared__ RefShared sh;
-  refine_body(a, blockIdx.x, sh);
+  refine_body<false>(a, blockIdx.x, sh);
+}
+
+// The same with each chunk's queue divided over a.split workgroups (small
+// fields: too few chunks to fill the chip).
+__global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))) void refine_split_kernel(RefArgs a) {
+  __shared__ RefShared sh;
+  refine_body<true>(a, blockIdx.x, sh);
 }
 
 // Whole-field replay of the schedule over every queued saddle, by one
@@ -3001,7 +3023,7 @@ __global__ __launch_bounds__(kRefThreads) __attribute__((amdgpu_waves_per_eu(4))
   const DecJob* jobs = reinterpret_cast<const DecJob*>(tab + tab_jobs_off(h->count));
   for_items(h->n_slot, [&](int it) {
     const int f = find_job(pre, h->count, it);
-    refine_body(jobs[f].ref, it - pre[f], sh);
+    refine_body<false>(jobs[f].ref, it - pre[f], sh);
   });
 }
 
@@ -3274,6 +3296,8 @@ int build_dec(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_
   ra.ws = d_ws;
   ra.status = d_status;
   *slots = xcd_grid((int)nch);
+  ra.slots = *slots;
+  ra.split = 1;
   return TOPOSZP_OK;
 }
 
@@ -3486,7 +3510,14 @@ int toposzp_decompress(const uint8_t* d_in, size_t in_size, float* d_out, size_t
     hipLaunchKernelGGL(decode_kernel<4>, dim3(slots), dim3(256), 0, s, J.dec);
   ev_end(3, s);
   ev_begin(4, s);
-  hipLaunchKernelGGL(refine_kernel, dim3(slots), dim3(kRefThreads), 0, s, J.ref);
+  // a small field divides each chunk's queue over up to 8 workgroups, so that
+  // the few chunks with many clusters do not each hold one workgroup alone
+  // (the division changes no result)
+  while (J.ref.split < 8 && slots * J.ref.split < 1024) J.ref.split *= 2;
+  if (J.ref.split > 1)
+    hipLaunchKernelGGL(refine_split_kernel, dim3(slots * J.ref.split), dim3(kRefThreads), 0, s, J.ref);
+  else
+    hipLaunchKernelGGL(refine_kernel, dim3(slots), dim3(kRefThreads), 0, s, J.ref);
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(256), 0, s, J.ref);
   ev_end(4, s);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
