@@ -24,7 +24,9 @@
 //                    schedule, so an isolated saddle is settled by a single
 //                    evaluation, and a cluster (gathered by one lane) is
 //                    replayed by the workgroup, one member per lane.  The
-//                    first workgroup also writes the call's status.
+//                    first workgroup also writes the call's status.  For a
+//                    small field, refine_split_kernel divides each chunk's
+//                    queue over up to 8 workgroups.
 //   tail_kernel      one workgroup: the same schedule for the rare clusters
 //                    of more than 64 members, gathered and replayed from
 //                    LDS (the whole field's queue when they do not fit).
