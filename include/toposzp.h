@@ -11,7 +11,8 @@
  * Conventions for every call below:
  *  - Pointers named d_* are DEVICE pointers (HIP global memory on the
  *    current device); h_* are host pointers.  The caller owns every buffer;
- *    the library never allocates, frees or retains memory.  Alignment: the
+ *    the library never allocates, frees or retains memory (one exception:
+ *    the scratch of toposzp_compress_noalloc).  Alignment: the
  *    input field 16 bytes, streams and sizes 8 bytes, the workspace 256
  *    bytes, reconstructions and statuses 4 bytes (TOPOSZP_E_INVALID_ARG
  *    otherwise).
@@ -126,6 +127,28 @@ int toposzp_compress(const float *d_field, uint32_t ndim, const uint64_t *dims,
                      void *d_ws, size_t ws_bytes, uint8_t *d_out,
                      size_t out_cap, uint64_t *d_out_size, int32_t *d_status,
                      void *stream);
+
+/* Allocation-free compression, for callers that cannot allocate device memory
+ * (work under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): toposzp_compress with block-scope ranks, minus the workspace.
+ * Its kernels use a scratch array inside the library instead, one per device
+ * (62,985,216 bytes, held from the library's load until the process ends);
+ * the call itself allocates and frees nothing.  The caller still owns the
+ * field, the output, the size and the status, with the meanings and
+ * alignments of toposzp_compress.
+ *  - Fields of at most TOPOSZP_NOALLOC_MAX_POINTS (2^24) points; larger ones
+ *    return TOPOSZP_E_CAPACITY before anything is enqueued.
+ *  - params.rank_scope 1 (field scope) returns TOPOSZP_E_UNSUPPORTED.
+ *  - Every call on a device shares that device's scratch, which keeps the last
+ *    call's contents (no call depends on them).  Calls on one device must be
+ *    ordered (one stream, or synchronised): calls that overlap race and give
+ *    undefined streams.
+ * The stream equals toposzp_compress's for the same arguments. */
+#define TOPOSZP_NOALLOC_MAX_POINTS (1ull << 24)
+int toposzp_compress_noalloc(const float *d_field, uint32_t ndim, const uint64_t *dims,
+                             int eb_mode, double eb, const toposzp_params *params,
+                             uint8_t *d_out, size_t out_cap, uint64_t *d_out_size,
+                             int32_t *d_status, void *stream);
 
 /* Decompression (Section IV-B): decoding to bin-centre values, metadata
  * extraction, the extrema stencil on flattened minima/maxima and iterated

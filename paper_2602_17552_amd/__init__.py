@@ -25,8 +25,9 @@ SYMBOLS = [
     "toposzp_compress_batch", "toposzp_decompress_batch", "toposzp_decompress_batch_stats",
     "toposzp_set_tuning", "toposzp_get_tuning", "toposzp_autotune_compress_batch",
     "toposzp_autotune_decompress_batch", "toposzp_eval", "toposzp_compress_bound_ex",
-    "toposzp_workspace_size_ex",
+    "toposzp_workspace_size_ex", "toposzp_compress_noalloc",
 ]
+NOALLOC_MAX_POINTS = 1 << 24
 
 
 class Params(C.Structure):
@@ -88,6 +89,9 @@ def lib():
         L.toposzp_compress.argtypes = [vp, C.c_uint32, u64p, C.c_int, C.c_double,
                                        C.POINTER(Params), vp, C.c_size_t, vp, C.c_size_t,
                                        vp, vp, vp]
+        L.toposzp_compress_noalloc.restype = C.c_int
+        L.toposzp_compress_noalloc.argtypes = [vp, C.c_uint32, u64p, C.c_int, C.c_double,
+                                               C.POINTER(Params), vp, C.c_size_t, vp, vp, vp]
         L.toposzp_decompress.restype = C.c_int
         L.toposzp_decompress.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp, vp]
         L.toposzp_compress_sync.restype = C.c_int
@@ -215,6 +219,25 @@ def compress_async(field, eb, mode="rel", ws=None, out=None, size=None, status=N
                                 _stream(stream))
     if rc != OK:
         raise RuntimeError(f"toposzp_compress: {strerror(rc)} ({rc})")
+    return out, size, status
+
+
+def compress_noalloc_async(field, out, size, status, eb, mode="rel", stream=None, **params):
+    """Enqueues the allocation-free compression (the library's scratch, no
+    workspace) into caller buffers: out uint8, size int64[1], status
+    int32[1], all CUDA tensors.  Fields of at most NOALLOC_MAX_POINTS points,
+    block-scope ranks only."""
+    import torch
+    if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
+        raise TypeError("field must be a contiguous float32 CUDA tensor")
+    shape = tuple(field.shape)
+    p = _params(**params)
+    rc = lib().toposzp_compress_noalloc(C.c_void_p(field.data_ptr()), len(shape), _dims(shape),
+                                        EB_REL if mode == "rel" else EB_ABS, float(eb), C.byref(p),
+                                        C.c_void_p(out.data_ptr()), out.numel(), C.c_void_p(size.data_ptr()),
+                                        C.c_void_p(status.data_ptr()), _stream(stream))
+    if rc != OK:
+        raise RuntimeError(f"toposzp_compress_noalloc: {strerror(rc)} ({rc})")
     return out, size, status
 
 

@@ -45,6 +45,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -134,8 +135,8 @@ struct CompLayout {
 // Rank planes per block the staging holds: 7 for block-scope ranks (at most
 // 64), 31 for field-scope ranks.
 __host__ __device__ constexpr int rank_w(int field) { return field ? kMaxWRankAny : kMaxWRankBlk; }
-__host__ __device__ inline CompLayout comp_layout(uint64_t nch, int field = 0) {
-  CompLayout L;
+__host__ __device__ constexpr CompLayout comp_layout(uint64_t nch, int field = 0) {
+  CompLayout L{};
   // three per-chunk arrays of u32, each padded to 16 bytes (read as uint4)
   const uint64_t arr = (4 * nch + 15) & ~uint64_t(15);
   L.tot_d = kRegionOff;
@@ -3177,7 +3178,8 @@ unsigned batch_grid(int items, int wgs_per_cu) {
 // Checks one compression request and fills its kernel arguments.
 int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode, double eb,
                const toposzp_params* params, uint8_t* d_ws, size_t ws_bytes, uint8_t* d_out, size_t out_cap,
-               uint64_t* d_out_size, int32_t* d_status, CompJob* J, bool allow_field = true) {
+               uint64_t* d_out_size, int32_t* d_status, CompJob* J, bool allow_field = true,
+               bool comp_only = false) {
   toposzp_params p = {64, 0, 0, 16, 1};
   if (params) p = *params;
   HostGeom hg;
@@ -3195,7 +3197,8 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   const int field = p.rank_scope == 1 && p.topo ? 1 : 0;
   if (field && !allow_field) return TOPOSZP_E_UNSUPPORTED;
   if (out_cap < toposzp_compress_bound_ex(ndim, dims, field)) return TOPOSZP_E_CAPACITY;
-  if (ws_bytes < (field ? ws_need_field(hg) : ws_need(hg))) return TOPOSZP_E_CAPACITY;
+  const size_t need = comp_only ? (size_t)al256(comp_layout(hg.nch).end) : field ? ws_need_field(hg) : ws_need(hg);
+  if (ws_bytes < need) return TOPOSZP_E_CAPACITY;
 
   int nrange = (int)((hg.g.n / 4 + 256 * kRangeVec - 1) / (256 * kRangeVec));
   if (nrange > kRangeWG) nrange = kRangeWG;
@@ -3373,6 +3376,36 @@ int autotune(const std::vector<toposzp_tuning>& cands, hipStream_t s, Run&& run,
   return rc;
 }
 
+// Scratch of the allocation-free compression call: the compression region
+// of a workspace for the largest field that call accepts.  Every device the
+// library runs on holds one copy until the process ends.
+constexpr uint64_t kNoAllocMaxPoints = 1ull << 24;
+constexpr size_t kScratchBytes = (size_t)al256(comp_layout(kNoAllocMaxPoints / kChunk).end);
+static_assert(kNoAllocMaxPoints / kChunk <= (uint64_t)kFuseMax, "the scratch path uses the fused scan");
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (host code must never pass the symbol itself to a kernel).
+std::mutex g_scratch_mu;
+std::atomic<uint8_t*> g_scratch[64];
+int scratch_of_device(uint8_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return TOPOSZP_E_DEVICE;
+  uint8_t* p = g_scratch[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      void* q = nullptr;
+      if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return TOPOSZP_E_DEVICE;
+      p = static_cast<uint8_t*>(q);
+      g_scratch[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return TOPOSZP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3493,6 +3526,33 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   if (!J.fin.fused) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, J.scan);
   hipLaunchKernelGGL(finalize_kernel, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, J.fin);
   ev_end(2, s);
+  return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
+}
+
+int toposzp_compress_noalloc(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb_mode, double eb,
+                             const toposzp_params* params, uint8_t* d_out, size_t out_cap, uint64_t* d_out_size,
+                             int32_t* d_status, void* stream) {
+  // host checks first: nothing touches the device for a rejected request
+  HostGeom hg;
+  int rc = host_geom(ndim, dims, &hg);
+  if (rc != TOPOSZP_OK) return rc;
+  if ((uint64_t)hg.g.n > kNoAllocMaxPoints) return TOPOSZP_E_CAPACITY;
+  if (params && params->rank_scope == 1 && params->topo) return TOPOSZP_E_UNSUPPORTED;
+  uint8_t* ws = nullptr;
+  rc = scratch_of_device(&ws);
+  if (rc != TOPOSZP_OK) return rc;
+  CompJob J;
+  rc = build_comp(d_field, ndim, dims, eb_mode, eb, params, ws, kScratchBytes, d_out, out_cap, d_out_size,
+                  d_status, &J, false, true);
+  if (rc != TOPOSZP_OK) return rc;
+  // the kernels of toposzp_compress on the scratch; each writes every byte
+  // of the scratch that a later one reads, so nothing there needs clearing
+  hipStream_t s = (hipStream_t)stream;
+  const EncArgs& ea = J.enc;
+  if (eb_mode == TOPOSZP_EB_REL)
+    hipLaunchKernelGGL(range_kernel, dim3(ea.nrange), dim3(256), 0, s, d_field, ea.gd.n, ws);
+  launch_encode((int)ndim, tune_now().encode_waves, xcd_grid(ea.nch), s, ea);
+  hipLaunchKernelGGL(finalize_kernel, dim3(xcd_grid(ea.nch)), dim3(256), 0, s, J.fin);
   return hipGetLastError() == hipSuccess ? TOPOSZP_OK : TOPOSZP_E_DEVICE;
 }
 
