@@ -27,9 +27,15 @@
  *    minimum, 1 + the number with a larger value; for a flattened saddle, 1.
  *    Every other point stores 0.  The decompressor only moves flattened
  *    extrema, so these ranks carry exactly the order it has to restore.
- *  - Stencil: eta is one float step (nextafterf), applied delta times, with
- *    pre-stencil values for every neighbour (Jacobi); a move is kept only if
- *    it stays within e of the bin centre.
+ *  - Lost points: the decoder takes them from the stream, an extremum or
+ *    saddle label with delta > 0.  On streams the compressor writes these are
+ *    exactly the labelled points that read as regular in the decoded field
+ *    (the paper's test), and a lost extremum's neighbour maximum (minimum) of
+ *    pre-stencil values is its own bin centre; every stream, canonical or
+ *    not, is decoded by this one rule.
+ *  - Stencil: eta is one float step (nextafterf), applied delta times from
+ *    the bin centre (the pre-stencil neighbour extreme); a move is kept only
+ *    if it stays within e of the bin centre.
  *  - RS: the candidate is the Gaussian-weighted mean of the window
  *    {q != p : |q - p|_2 <= floor(k/2)} (convex weights, Eq. (2)); it is kept
  *    only if it stays within e of the bin centre, makes p a saddle again and
@@ -38,19 +44,26 @@
  *    a phase) repeat until a round commits nothing or max_rounds is reached.
  *    k_size and sigma are chosen from the mean block bit width.
  *
- * What pins each part (tests/test_oracle_*.py):
+ * What pins each part (tests/test_oracle_*.py, tests/test_stream_format.py):
  *  - QZ: exact-rational recomputation of the defining inequality, the
  *    worked example of Section III-A (Fig. 2), bin edges and power-of-two e.
  *  - CD: an independently written numpy classifier, closed-form critical point
  *    densities of i.i.d. noise (2D: 1/5, 1/5, 1/15; 3D: 1/7, 1/7, 2/35).
- *  - RP: the Fig. 5 example (M1 < M2 in bin 1 get ranks 1 and 2).
- *  - Codec: lossless round trip, widths and signs against direct definitions.
+ *  - RP: the Fig. 5 example (M1 < M2 in bin 1 get ranks 1 and 2); the sign
+ *    of every same-bin pair of restored minima and maxima against the
+ *    original values; a kept and two lost maxima in one bin and block.
+ *  - Codec and layout: lossless round trip, widths and signs against direct
+ *    definitions, every header field and segment against the format table.
  *  - Stencil/RS: no false positives or false types (Section III-B argument,
  *    Table II), lost extrema all restored when the budget allows (Section V),
  *    |a - a^| <= 2e (Section V), single-bin and wide-gap special cases
- *    (Section IV-B), brute force over every 3x3 field on a 5-value alphabet.
- *  - Byte layout of the stream: parity unpinned against the paper, which
- *    gives only the list of parts; pinned by the format description.
+ *    (Section IV-B), brute force over every 3x3 field on a 5-value alphabet;
+ *    isolated refined saddles against the exact-rational Gaussian mean over
+ *    the Euclidean ball (k = 5, 7 in 2D and 3D); one-round pairs against the
+ *    Jacobi-within-phase, colour-ordered schedule.
+ *  - Evaluation: a recount with the numpy classifier.
+ *  - Byte layout of the stream: the paper gives only the list of parts, so
+ *    it is pinned by the format table, not by the paper.
  */
 #include "toposzp_oracle.h"
 
@@ -686,8 +699,7 @@ int ora_decompress(const uint8_t *in, size_t in_size, float *out,
   int64_t n = g.n;
   int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   int32_t *delta = NULL;
-  uint8_t *label = NULL, *cls = NULL;
-  float *pre = NULL;
+  uint8_t *label = NULL;
   int64_t *work = NULL, *acc_i = NULL;
   float *acc_v = NULL;
 
@@ -708,23 +720,24 @@ int ora_decompress(const uint8_t *in, size_t in_size, float *out,
   for (int64_t i = 0; i < n; i++)
     label[i] = (uint8_t)((in[h.off[SEG_S6] + (uint64_t)(i >> 2)] >> (2 * (i & 3))) & 3u);
 
-  /* CP + RP: extrema stencil on lost extrema, from pre-stencil values */
-  cls = (uint8_t *)malloc((size_t)n);
-  pre = (float *)malloc(sizeof(float) * (size_t)n);
-  memcpy(pre, out, sizeof(float) * (size_t)n);
-  for (int64_t i = 0; i < n; i++) cls[i] = (uint8_t)classify_at(pre, &g, i, -1, 0.0f);
+  /* CP + RP: the extrema stencil.  The lost critical points are the ones
+   * the stream marks with delta > 0 (an extremum or saddle label); the
+   * compressor marks exactly those with a face neighbour in their own bin,
+   * which are exactly the critical points that read as regular in the
+   * decoded field (R is strictly increasing, so every strict neighbour order
+   * across bins survives and every tie within a bin breaks the point).  For
+   * a lost maximum every neighbour's decoded value is at most its own bin
+   * centre and one equals it, so the neighbour maximum of the paper's
+   * stencil is the point's own centre R(q); likewise the neighbour minimum
+   * of a lost minimum.  The decoder therefore reads both from the stream
+   * instead of reclassifying: delta float steps up (maximum) or down
+   * (minimum) from R(q), kept only within e of R(q).  A stream that marks
+   * other points (the compressor never writes one) is decoded by the same
+   * rule. */
   for (int64_t i = 0; i < n; i++) {
-    if ((label[i] != ORA_MIN && label[i] != ORA_MAX) || cls[i] == label[i]) continue;
-    int64_t nb[6];
-    int k = face_neighbours(&g, i, nb);
-    if (k == 0) continue;
-    float m = pre[nb[0]];
-    for (int j = 1; j < k; j++) {
-      if (label[i] == ORA_MAX && pre[nb[j]] > m) m = pre[nb[j]];
-      if (label[i] == ORA_MIN && pre[nb[j]] < m) m = pre[nb[j]];
-    }
-    float v = float_steps(m, delta[i], label[i] == ORA_MAX);
+    if ((label[i] != ORA_MIN && label[i] != ORA_MAX) || delta[i] == 0) continue;
     float rq = ora_recon(q[i], h.e);
+    float v = float_steps(rq, delta[i], label[i] == ORA_MAX);
     if (fabs((double)v - (double)rq) <= (double)h.e) {
       out[i] = v;
       st->stencil_moves++;
@@ -755,8 +768,10 @@ int ora_decompress(const uint8_t *in, size_t in_size, float *out,
     work = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     acc_i = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     acc_v = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    /* the lost saddles, as the stream marks them; one that the stencil has
+     * already made a saddle again is skipped by every round below */
     for (int64_t i = 0; i < n; i++)
-      if (label[i] == ORA_SAD && classify_at(out, &g, i, -1, 0.0f) != ORA_SAD) work[nw++] = i;
+      if (label[i] == ORA_SAD && delta[i] > 0) work[nw++] = i;
     st->worklist0 = nw;
     for (int round = 1; round <= h.max_rounds; round++) {
       int64_t commits = 0;
@@ -809,8 +824,6 @@ done:
   free(q);
   free(delta);
   free(label);
-  free(cls);
-  free(pre);
   free(work);
   free(acc_i);
   free(acc_v);

@@ -48,7 +48,7 @@ typedef struct {
 typedef struct {
   int64_t rounds;         /* RBF rounds executed */
   int64_t commits;        /* RBF updates committed, all rounds */
-  int64_t worklist0;      /* lost saddles after the extrema stencil */
+  int64_t worklist0;      /* saddles the stream marks lost (delta > 0) */
   int64_t stencil_moves;  /* extrema moved by the stencil */
   int64_t budget_skips;   /* lost extrema left unmoved by the error budget */
 } ora_stats;

@@ -63,6 +63,7 @@ def check(tsz, ora, name, f, eb, mode="rel", **params):
         name, bad.size, bad[0], rec_g.reshape(-1)[bad[0]], rec_o.reshape(-1)[bad[0]])
     for k in ("rounds", "commits", "stencil_moves", "budget_skips"):
         assert stats_g[k] == stats_o[k], (name, k, stats_g, stats_o)
+    assert stats_g["queued"] == stats_o["worklist0"], (name, stats_g, stats_o)
     return s_o, rec_o, stats_o
 
 
