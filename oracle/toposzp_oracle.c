@@ -672,6 +672,9 @@ static int decode_stream(const uint8_t *in, const hdr_t *h, int s1, int s2,
     planes_done += (uint64_t)w;
   }
   if (8 * planes_done != h->len[s5]) return ORA_E_CORRUPT;
+  /* the bitmap's bits past the last block are 0 */
+  for (uint64_t b = h->nb; b < 64 * h->nch; b++)
+    if ((in[h->off[s1] + b / 8] >> (b % 8)) & 1) return ORA_E_CORRUPT;
   return ORA_OK;
 }
 

@@ -151,3 +151,54 @@ def with_ranks(b: bytes, delta: np.ndarray) -> bytes:
     struct.pack_into("<Q", out, 264 + 8 * SEGS.index("R5"), lens["R5"])
     struct.pack_into("<I", out, SUMMED, zlib.adler32(bytes(out[:SUMMED])))
     return bytes(out)
+
+
+def corruptions(b: bytes):
+    """(name, stream) pairs, each breaking one segment rule of the table
+    while the header stays valid: chunk offsets, constant bitmaps (a wrong
+    bit, a bit past the last block), widths, a first value out of the bin
+    index range, and a truncated stream.  Needs a topology stream of more
+    than one chunk whose last chunk is partial."""
+    h = parse_header(b)
+    assert h["topo"] == 1 and h["nch"] >= 2 and h["nb"] % 64 != 0
+    out = []
+
+    def put(name, segname, off, fmt, value):
+        t = bytearray(b)
+        struct.pack_into(fmt, t, h["off"][segname] + off, value)
+        out.append((name, bytes(t)))
+
+    x1 = np.frombuffer(seg(b, h, "X1"), "<u8")
+    x2 = np.frombuffer(seg(b, h, "X2"), "<u8")
+    put("X1 chunk 1 off by 8", "X1", 8, "<Q", int(x1[1]) + 8)
+    put("X1 chunk 0 not 0", "X1", 0, "<Q", 8)
+    put("X1 last past S5", "X1", 8 * (h["nch"] - 1), "<Q", h["len"]["S5"] + 8)
+    put("X2 chunk 1 off by 8", "X2", 8, "<Q", int(x2[1]) + 8)
+    put("X2 chunk 1 minus 8", "X2", 8, "<Q", max(int(x2[1]) - 8, 0) if int(x2[1]) else 8)
+    widths = np.frombuffer(seg(b, h, "S2"), np.uint8)
+    rwidths = np.frombuffer(seg(b, h, "R2"), np.uint8)
+    k = int(np.nonzero(widths)[0][0])
+    t = bytearray(b)
+    t[h["off"]["S1"] + k // 8] ^= 1 << (k % 8)
+    out.append(("S1 bit set on a coded block", bytes(t)))
+    nz = np.nonzero(rwidths == 0)[0]
+    k = int(nz[0])
+    t = bytearray(b)
+    t[h["off"]["R1"] + k // 8] ^= 1 << (k % 8)
+    out.append(("R1 bit cleared on a constant block", bytes(t)))
+    for segname in ("S1", "R1"):
+        t = bytearray(b)
+        k = h["nb"]  # first block past the end
+        t[h["off"][segname] + k // 8] |= 1 << (k % 8)
+        out.append((segname + " bit past the last block", bytes(t)))
+    put("S2 width 24", "S2", 0, "<B", 24)
+    put("S2 width +1", "S2", int(np.argmax(widths)), "<B", int(widths.max()) + 1)
+    put("R2 width 32", "R2", 1, "<B", 32)
+    put("R2 width +1", "R2", int(np.argmax(rwidths)), "<B", int(rwidths.max()) + 1)
+    put("S4 first value 2^22", "S4", 4, "<i", 1 << 22)
+    put("S4 first value -2^22", "S4", 0, "<i", -(1 << 22))
+    put("R4 rank 65", "R4", 8, "<i", 65)
+    put("R4 rank -1", "R4", 0, "<i", -1)
+    out.append(("truncated by one byte", b[:-1]))
+    out.append(("truncated to the header", b[:HDR]))
+    return out

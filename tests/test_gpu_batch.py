@@ -59,6 +59,31 @@ def test_batch_matches_oracle_and_single(tsz, ora):
             assert sg[k] == stats_o[k], (i, k, sg, stats_o)
 
 
+def test_batch_scan_path(tsz, ora):
+    """A job of more than 4096 chunks (16,842,752 points) beside small ones:
+    the batch's separate scan kernel and the unfused finalize, against the
+    oracle byte for byte and bit for bit."""
+    import torch
+    fields = [datagen.grf_3d(257, 256, 256, seed=2), datagen.gaussian_bumps_2d(70, 90, 6, seed=23),
+              datagen.grf_3d(20, 22, 24, seed=24)]
+    ebs = [1e-3, 1e-2, 3e-3]
+    b, st, streams = _run_batch(tsz, fields, ebs)
+    assert st == [0] * len(fields)
+    d = tsz.DecompressBatch([torch.from_numpy(s).cuda() for s in streams], [f.shape for f in fields])
+    d.run()
+    torch.cuda.synchronize()
+    assert d.status.cpu().tolist() == [0] * len(fields)
+    for i, (f, eb) in enumerate(zip(fields, ebs)):
+        print("scan-path batch job %d %s" % (i, f.shape), flush=True)
+        rc, s_o = ora.compress(f, eb, "rel")
+        assert rc == 0 and np.array_equal(streams[i], s_o), i
+        rc, rec_o, stats_o = ora.decompress(s_o, f.shape)
+        assert np.array_equal(d.recs[i].cpu().numpy().view(np.uint32), rec_o.view(np.uint32)), i
+        sg = d.stats(i)
+        for k in ("rounds", "commits", "stencil_moves", "budget_skips"):
+            assert sg[k] == stats_o[k], (i, k, sg, stats_o)
+
+
 def test_batch_mixed_modes_and_params(tsz, ora):
     fields = [datagen.noise((33, 47), seed=3), datagen.grf_3d(9, 10, 11, seed=4),
               datagen.gaussian_bumps_2d(70, 130, 8, seed=5), datagen.noise((1, 1), seed=6),

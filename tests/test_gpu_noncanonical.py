@@ -84,3 +84,19 @@ def test_rank_out_of_range_is_corrupt_on_both(tsz, ora):
         rc_o, _, _ = ora.decompress(s2, f.shape)
         st_g, _, _ = gpu_decompress(tsz, s2, f.shape)
         assert rc_o == st_g == ora.E_CORRUPT, (pos, val, rc_o, st_g)
+
+
+def test_segment_corruption_on_both(tsz, ora):
+    """Each segment rule of the format table broken once (chunk offsets,
+    constant bitmaps, widths, first values, ranks, truncation): both decoders
+    report the stream corrupt.  The GPU decoder checks widths, bitmaps and
+    chunk offsets before it reads a chunk's planes, and reads only inside the
+    header-checked layout."""
+    f = datagen.sinusoids_2d(75, 120, 8, seed=9)
+    rc, s = ora.compress(f, 5e-3, "rel")
+    for name, t in sf.corruptions(bytes(s)):
+        print("corruption:", name, flush=True)
+        arr = np.frombuffer(t, np.uint8).copy()
+        rc_o, _, _ = ora.decompress(arr, f.shape)
+        st_g, _, _ = gpu_decompress(tsz, arr, f.shape)
+        assert rc_o == st_g == ora.E_CORRUPT, (name, rc_o, st_g)

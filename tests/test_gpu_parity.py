@@ -99,21 +99,24 @@ def test_parity_shapes(tsz, ora, shape):
 
 
 def test_parity_kernel_sizes(tsz, ora):
-    """Adaptive k_size 7 / 5 (two-step phases in 2D for 7, in 3D for 5 and 7)
-    and the fixed k_size 3 policy."""
+    """Every adaptive window: k_size 3, 5 and 7 in 2D and in 3D (the fields
+    and bounds below are chosen to reach each one), the fixed k_size 3
+    policy and a one-round cap."""
     smooth = datagen.gaussian_bumps_2d(120, 150, 4, seed=11, noise_sd=2e-4)
-    r = check(tsz, ora, "smooth_k", smooth, 1e-3, "rel")
-    s3 = datagen.grf_3d(24, 20, 18, seed=12, slope=-4.0)
-    check(tsz, ora, "smooth3d_k", s3, 2e-3, "abs")
-    check(tsz, ora, "smooth3d_k_coarse", s3, 2e-2, "abs")
+    waves = datagen.sinusoids_2d(80, 96, 8, seed=12, noise_sd=2e-3)
+    checker = datagen.checker_2d(60, 64, seed=1)
+    g3 = datagen.grf_3d(24, 28, 32, seed=13)
+    cases = [("waves_k3", waves, 1e-2), ("waves_k5", waves, 5e-2), ("checker_k7", checker, 0.3),
+             ("grf3d_k3", g3, 3e-2), ("grf3d_k5", g3, 0.1), ("grf3d_k7", g3, 0.3)]
+    ks = set()
+    for name, f, eb in cases:
+        s_o, _, _ = check(tsz, ora, name, f, eb, "rel")
+        ks.add((f.ndim, ora.inspect(s_o)[1]["k"]))
+    print("kernel sizes covered:", sorted(ks), flush=True)
+    assert ks == {(2, 3), (2, 5), (2, 7), (3, 3), (3, 5), (3, 7)}
     check(tsz, ora, "fixed3", smooth, 1e-3, "rel", rbf_policy=1)
     check(tsz, ora, "rounds1", smooth, 1e-3, "rel", max_rounds=1)
-    ks = set()
-    for f, eb, mode in [(smooth, 1e-3, "rel"), (smooth, 3e-2, "rel"), (s3, 2e-3, "abs"), (s3, 2e-2, "abs")]:
-        rc, s = ora.compress(f, eb, mode)
-        ks.add((f.ndim, ora.inspect(s)[1]["k"]))
-    print("kernel sizes covered:", sorted(ks), flush=True)
-    assert len(ks) >= 3
+    check(tsz, ora, "checker_k7_rounds1", checker, 0.3, "rel", max_rounds=1)
 
 
 def _checker_patches(m, counts, gap=4):
@@ -294,13 +297,19 @@ FULL = [
     ("cfg1_1800x3600_rel5e-2_k7", datagen.cfg1, 5e-2),   # the widest window, at scale
     ("cfg2_256cube_rel1e-3", datagen.cfg2, 1e-3),
     ("cfg2_256cube_rel3e-2_k5", datagen.cfg2, 3e-2),     # a 3D k=5 window, at scale
+    # the widest 3D window (k=7, 122 cells) on a field of 512 chunks
+    ("grf_128cube_rel0.3_k7", lambda: datagen.grf_3d(128, 128, 128, seed=21), 0.3),
+    # more than 4096 chunks (16,842,752 points): the separate scan kernel and
+    # the unfused finalize
+    ("grf_257x256x256_rel1e-3_scan", lambda: datagen.grf_3d(257, 256, 256, seed=2), 1e-3),
+    ("waves_4100x4100_rel1e-3_scan", lambda: datagen.sinusoids_2d(4100, 4100, 64, seed=22), 1e-3),
 ]
 _cache = {}
 
 
 @pytest.mark.parametrize("name,gen,eb", FULL, ids=[c[0] for c in FULL])
 def test_parity_full_size(tsz, ora, name, gen, eb):
-    key = gen.__name__
+    key = gen.__name__ if gen.__name__ != "<lambda>" else name
     if key not in _cache:
         _cache.clear()
         _cache[key] = gen()

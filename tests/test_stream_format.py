@@ -200,3 +200,19 @@ def test_rank_out_of_range_is_corrupt(ora):
     d2[7] = -1
     rc, _, _ = ora.decompress(np.frombuffer(sf.with_ranks(b, d2), np.uint8), f.shape)
     assert rc == ora.E_CORRUPT
+
+
+def _corrupt_source(ora):
+    f = datagen.sinusoids_2d(75, 120, 8, seed=9)  # 141 blocks: 3 chunks, the last partial
+    rc, s = ora.compress(f, 5e-3, "rel")
+    assert rc == ora.OK
+    return f, bytes(s)
+
+
+def test_segment_corruption_is_reported(ora):
+    f, b = _corrupt_source(ora)
+    cases = sf.corruptions(b)
+    assert len(cases) >= 18
+    for name, t in cases:
+        rc, _, _ = ora.decompress(np.frombuffer(t, np.uint8).copy(), f.shape)
+        assert rc == ora.E_CORRUPT, name
