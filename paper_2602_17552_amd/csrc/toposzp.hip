@@ -142,6 +142,7 @@ __host__ __device__ constexpr CompLayout comp_layout(uint64_t nch, int field = 0
   L.tot_d = kRegionOff;
   L.tot_r = L.tot_d + arr;
   L.cflag = L.tot_r + arr;
+  // staged planes: one slot per block (its planes at the slot's start)
   L.stage_d = al256(L.cflag + arr);
   L.stage_r = al256(L.stage_d + 8ull * kB * kMaxWData * nch);
   L.end = al256(L.stage_r + 8ull * kB * rank_w(field) * nch);
@@ -353,6 +354,51 @@ __device__ __forceinline__ int encode_block(int v, int lane, unsigned* dst,
   if (lane < 2 * w) dst[lane] = (unsigned)mine;
   first = __builtin_amdgcn_readfirstlane(v);
   return w;
+}
+
+// The float32 products pm*e and pp*e rounded toward +infinity (the smallest
+// floats >= the exact products).  The two multiplies run with the f32
+// rounding mode set to round-up and the mode is restored at once; nothing
+// else runs in between.
+__device__ __forceinline__ void mul_round_up2(float pm, float pp, float e, float& lo, float& hi) {
+  asm volatile(
+      "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 2), 1\n\t"
+      "s_nop 1\n\t"
+      "v_mul_f32 %0, %2, %4\n\t"
+      "v_mul_f32 %1, %3, %4\n\t"
+      "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 2), 0\n\t"
+      "s_nop 1"
+      : "=&v"(lo), "=&v"(hi)
+      : "v"(pm), "v"(pp), "v"(e));
+}
+
+// Bit planes of a block (BE), the lanes' magnitudes `mag` of width w <=
+// MAXW: plane j is the ballot of bit j, kept in lanes 2j (low word) and
+// 2j+1 (high word) and written to dst[0, 2w).  Each plane is nested in the
+// previous one's test, so that a block of width w tests w + 1 conditions.
+template <int J, int MAXW>
+__device__ __forceinline__ void plane_run(unsigned mag, int w, int& mine) {
+  if constexpr (J < MAXW) {
+    if (J < w) {
+      const unsigned long long pl = __ballot((mag >> J) & 1u);
+      mine = llvm_writelane((int)(unsigned)pl, 2 * J, mine);
+      mine = llvm_writelane((int)(unsigned)(pl >> 32), 2 * J + 1, mine);
+      plane_run<J + 1, MAXW>(mag, w, mine);
+    }
+  }
+}
+template <int MAXW>
+__device__ __forceinline__ void put_planes(unsigned mag, int w, unsigned* dst, int lane) {
+  int mine = 0;
+  plane_run<0, MAXW>(mag, w, mine);
+  if (lane < 2 * w) dst[lane] = (unsigned)mine;
+}
+
+// |x - y| of unsigned values (v_sad_u32).
+__device__ __forceinline__ unsigned absdiff_u32(unsigned x, unsigned y) {
+  unsigned d;
+  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(d) : "v"(x), "v"(y));
+  return d;
 }
 
 // Inverse: each lane reads its own 32-bit half of every plane (lanes 0-31
@@ -667,20 +713,57 @@ __device__ __forceinline__ EncIn enc_fetch(const float* __restrict__ f, int b, i
   return r;
 }
 
+// f(std::integral_constant<int, K>) for K = K0 .. N-1: a loop whose index is
+// a compile-time constant in every iteration.
+template <int K, int N, typename F>
+__device__ __forceinline__ void unroll(F&& f) {
+  if constexpr (K < N) {
+    f(std::integral_constant<int, K>{});
+    unroll<K + 1, N>(f);
+  }
+}
+
+// The values of enc_fetch for block k of a wave whose first block starts at
+// p, when every read of the wave lies inside the field: uniform base
+// addresses plus the lane's offset, the block's offset a constant of the
+// load instructions.  xoff is 0 for lane 0 (the value before the block) and
+// 65 for the others (the value after it, seen from one before the block).
+template <int ND>
+__device__ __forceinline__ EncIn enc_fetch_wave(const float* __restrict__ p, int k, unsigned lane, unsigned xoff,
+                                                const GeomD& g) {
+  EncIn r;
+  const unsigned o = lane + (unsigned)(k * kB);
+  r.c = p[o];
+  r.ym = (p - g.nx)[o];
+  r.yp = (p + g.nx)[o];
+  if (ND == 3) {
+    r.zm = (p - g.nxy)[o];
+    r.zp = (p + g.nxy)[o];
+  } else {
+    r.zm = r.zp = 0.0f;
+  }
+  r.xe = (p - 1)[xoff + (unsigned)(k * kB)];
+  return r;
+}
+
+// Whether every read of block b lies inside the field.
+template <int ND>
+__device__ __forceinline__ bool reads_inside(int b, const GeomD& g) {
+  const int b0 = b * kB, st = ND == 3 ? g.nxy : g.nx;
+  return b0 - st >= 0 && b0 >= 1 && b0 + (kB - 1) + st <= g.n - 1 && b0 + kB <= g.n - 1;
+}
+
 // LDS of the encode kernel (one per workgroup, whatever the dimension);
 // MAXWR = widest rank planes (block or field scope).
 template <int MAXWR>
 struct EncSharedT {
-  unsigned pd[kB][2 * kMaxWData];  // a block's data planes, 2 words each
-  unsigned pr[kB][2 * MAXWR];      // its rank planes
   unsigned long long sign[kB], rsign[kB];
   int first[kB], rfirst[kB];
   unsigned lab[kB * 4];
   int wd[kB], wr[kB];
   int pfd[kB + 1], pfr[kB + 1];
   RangeSh rs;
-  float e;
-  unsigned flags;
+  unsigned wfl[16];  // each wave's error flags
 };
 
 using EncShared = EncSharedT<kMaxWRankBlk>;
@@ -703,33 +786,78 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   const float* __restrict__ f = a.f;
   const bool topo = a.topo != 0;
   const int bw = c * kB + wv * BPW;  // this wave's first block
+  // each block's planes go to its own staging slot (finalize gathers them)
+  const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
+  unsigned* stg_d = reinterpret_cast<unsigned*>(a.ws + L.stage_d);
+  unsigned* stg_r = reinterpret_cast<unsigned*>(a.ws + L.stage_r);
 
-  // the first four blocks' loads go out before the bound is known
-  EncIn P0 = enc_fetch<ND>(f, bw + 0, lane, g);
-  EncIn P1 = enc_fetch<ND>(f, bw + 1, lane, g);
-  EncIn P2 = enc_fetch<ND>(f, bw + 2, lane, g);
-  EncIn P3 = enc_fetch<ND>(f, bw + 3, lane, g);
+  // interior blocks of a topology stream in block scope take block_fast
+  // (below) when the field is at least 64 wide
+  const bool fast_mode = MODE == kModeBlock && topo && g.nx >= kB;
+  // a wave whose blocks read only inside the field loads without clamping
+  const bool inner = fast_mode && reads_inside<ND>(bw, g) && reads_inside<ND>(bw + BPW - 1, g);
+  const unsigned xoff = lane == 0 ? 0u : 65u;
+  const float* __restrict__ pw = f + (size_t)bw * kB;
+  // (two versions of the wave loop below, one per kind of load)
+  auto fetch_inner = [&](int k) -> EncIn { return enc_fetch_wave<ND>(pw, k, (unsigned)lane, xoff, g); };
+  auto fetch_clamped = [&](int k) -> EncIn { return enc_fetch<ND>(f, bw + k, lane, g); };
+  // Block k of the wave (lane k computes it) is interior when every point
+  // has both y (and z) neighbours; it then lies in one row, or in two
+  // consecutive rows of one plane (nx >= 64).  xbm marks interior blocks
+  // with a point at x = 0 or x = nx - 1; l0, l1 are the lanes of those
+  // points in block k.
+  unsigned long long fastm = 0, xbm = 0;
+  int l0v = 0, l1v = 0;
+  if (fast_mode) {
+    const int b = bw + (lane < BPW ? lane : 0);
+    const int b0 = b * kB, t = fdiv(b0, g.dx), x = b0 - t * g.nx;
+    int y = t;
+    bool ok = lane < BPW && b < a.nb;
+    if (ND == 3) {
+      const int z = fdiv(t, g.dy);
+      y = t - z * g.ny;
+      ok = ok && z >= 1 && z <= g.nz - 2;
+    }
+    const int xe = x + kB - 1;
+    ok = ok && y >= 1 && y + (xe >= g.nx ? 1 : 0) <= g.ny - 2;
+    const bool xb = x == 0 || xe >= g.nx - 1;
+    fastm = __ballot(ok && !xb);
+    xbm = __ballot(ok && xb);
+    l0v = x == 0 ? 0 : g.nx - x;
+    l1v = g.nx - 1 - x;
+  }
 
-  {
-    float e, vmin, vmax;
+  // The bound of this call, from the whole workgroup (call_bound; every
+  // wave calls this exactly once, after its first loads are out).
+  float e = 0.0f, inv2e = 0.0f;
+  double ed = 0.0;
+  unsigned wflag = 0;  // this wave's error flags
+  auto get_bound = [&]() {
+    float vmin, vmax;
     double eps;
     bool nf;
     call_bound(a.ws, a.eb_mode, a.eb, a.e_abs, a.nrange, sh.rs, &e, &vmin, &vmax, &eps, &nf);
-    if (tid == 0) {
-      sh.e = e;
-      sh.flags = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
-    }
-  }
-  __syncthreads();
-  const float e = sh.e;
-  const double ed = (double)e;
-  const float inv2e = 1.0f / (2.0f * e);
+    ed = (double)e;
+    inv2e = 1.0f / (2.0f * e);
+    wflag = (e >= 0x1p-100f && e <= 0x1p100f) ? 0u : 2u;
+  };
   const int n = g.n;
   const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
   unsigned long long nfm = 0, qom = 0;  // lanes with a non-finite value, |q| too large
   bool wover = false;
 
   const unsigned lab_shift = 2u * (unsigned)(lane & 15);
+  const unsigned lab_b0 = 1u << lab_shift, lab_b1 = 2u << lab_shift;
+  // this wave's slots in the per-block LDS arrays (block k of the wave at
+  // index k; the label dword of lanes 16j..16j+15 at 4k + j)
+  const int lb0 = wv * BPW;
+  int* const wd_w = sh.wd + lb0;
+  int* const wr_w = sh.wr + lb0;
+  int* const first_w = sh.first + lb0;
+  int* const rfirst_w = sh.rfirst + lb0;
+  unsigned long long* const sign_w = sh.sign + lb0;
+  unsigned long long* const rsign_w = sh.rsign + lb0;
+  unsigned* const lab_w = sh.lab + 4 * lb0 + (lane >> 4);
   int wcnt = 0;  // mark pass: entries in this wave's slice
   auto block = [&](const EncIn& in, int b) {
     const int lb = b - c * kB;
@@ -857,7 +985,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
 
     unsigned long long sign;
     int first;
-    const int w = encode_block<kMaxWData>(q, lane, sh.pd[lb], sign, first, wover);
+    const int w = encode_block<kMaxWData>(q, lane, stg_d + (size_t)b * 2 * kMaxWData, sign, first, wover);
     if (lane == 0) {
       sh.wd[lb] = w;
       sh.sign[lb] = sign;
@@ -873,7 +1001,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       unsigned long long rsign;
       int rfirst;
       bool rover = false;
-      const int wr = encode_block<MAXWR>(delta, lane, sh.pr[lb], rsign, rfirst, rover);
+      const int wr = encode_block<MAXWR>(delta, lane, stg_r + (size_t)b * 2 * MAXWR, rsign, rfirst, rover);
       if (lane == 0) {
         sh.wr[lb] = wr;
         sh.rsign[lb] = rsign;
@@ -884,18 +1012,184 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     }
   };
 
-  // four blocks in flight per wave: each buffer is refilled as soon as its
-  // block has been encoded (the last refills repeat the wave's last block)
-  const int blast = bw + BPW - 1;
-  for (int k = 0; k < BPW; k += 4) {
-    block(P0, bw + k);
-    P0 = enc_fetch<ND>(f, min(bw + k + 4, blast), lane, g);
-    block(P1, bw + k + 1);
-    P1 = enc_fetch<ND>(f, min(bw + k + 5, blast), lane, g);
-    block(P2, bw + k + 2);
-    P2 = enc_fetch<ND>(f, min(bw + k + 6, blast), lane, g);
-    block(P3, bw + k + 3);
-    P3 = enc_fetch<ND>(f, min(bw + k + 7, blast), lane, g);
+  // An interior block (see fast_mode below) in block scope: the same parts
+  // as `block` with fewer instructions.  The bin index comes from a float
+  // estimate t whose exact float edges lo = (2t-1)e and hi = (2t+1)e,
+  // rounded up, decide both the point's own bin (t is its bin iff
+  // lo <= a < hi) and its neighbours' (a neighbour shares the bin iff it
+  // lies in [lo, hi)): for a float x and a real L, x >= L iff x >= the
+  // smallest float >= L.  Returns false, having written nothing, when some
+  // lane's estimate is off, out of the bin index range or not finite; the
+  // caller then runs `block`.
+  auto block_fast = [&](const EncIn& in, auto kc, auto xbc, unsigned long long xm0, unsigned long long xm1) -> bool {
+    constexpr bool xb = decltype(xbc)::value;
+    const int k = kc;  // a compile-time constant in the unrolled loop
+    const int b = bw + k;
+    const float av = in.c;
+    const float t = rintf(av * inv2e);
+    float lo, hi;
+    mul_round_up2(fmaf(t, 2.0f, -1.0f), fmaf(t, 2.0f, 1.0f), e, lo, hi);
+    if (~(__ballot(av >= lo) & __ballot(av < hi) & __ballot(fabsf(t) <= (float)kQMax)) != 0ull) return false;
+    const int q = (int)t;
+    // classification (Section III-A): strict compares with the face
+    // neighbours; the x neighbours come from the adjacent lanes
+    const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(in.xe)));
+    const float xr = __int_as_float(dpp_from_next(__float_as_int(av), __float_as_int(in.xe)));
+    unsigned long long g0 = __ballot(xl > av), l0 = __ballot(xl < av);
+    unsigned long long g1 = __ballot(xr > av), l1 = __ballot(xr < av);
+    const unsigned long long g2 = __ballot(in.ym > av), l2 = __ballot(in.ym < av);
+    const unsigned long long g3 = __ballot(in.yp > av), l3 = __ballot(in.yp < av);
+    // flattened by plain SZp iff some face neighbour lies in [lo, hi)
+    unsigned long long sx = (__ballot(xl >= lo) & __ballot(xl < hi)), sx1 = (__ballot(xr >= lo) & __ballot(xr < hi));
+    unsigned long long same = (__ballot(in.ym >= lo) & __ballot(in.ym < hi)) |
+                              (__ballot(in.yp >= lo) & __ballot(in.yp < hi));
+    unsigned long long m_min, m_max;
+    if constexpr (xb) {
+      // a lane at x = 0 has no x- neighbour, one at x = nx - 1 no x+
+      // neighbour: extrema ignore it, a saddle needs the pair complete
+      g0 &= xm0;
+      l0 &= xm0;
+      g1 &= xm1;
+      l1 &= xm1;
+      sx &= xm0;
+      sx1 &= xm1;
+      m_min = (g0 | ~xm0) & (g1 | ~xm1);
+      m_max = (l0 | ~xm0) & (l1 | ~xm1);
+    } else {
+      m_min = g0 & g1;
+      m_max = l0 & l1;
+    }
+    same |= sx | sx1;
+    const unsigned long long bgx = g0 & g1, blx = l0 & l1, bgy = g2 & g3, bly = l2 & l3;
+    m_min &= bgy;
+    m_max &= bly;
+    unsigned long long m_sad;
+    if (ND == 3) {
+      const unsigned long long g4 = __ballot(in.zm > av), l4 = __ballot(in.zm < av);
+      const unsigned long long g5 = __ballot(in.zp > av), l5 = __ballot(in.zp < av);
+      const unsigned long long bgz = g4 & g5, blz = l4 & l5;
+      m_min &= bgz;
+      m_max &= blz;
+      m_sad = (bgx | blx) & (bgy | bly) & (bgz | blz) & (bgx | bgy | bgz) & (blx | bly | blz);
+      same |= (__ballot(in.zm >= lo) & __ballot(in.zm < hi)) | (__ballot(in.zp >= lo) & __ballot(in.zp < hi));
+    } else {
+      m_sad = (bgx & bly) | (blx & bgy);
+    }
+    const unsigned long long lostm = (m_min | m_max | m_sad) & same;
+    // ranks (Section IV-A (2)), as in `block`; with at most one flattened
+    // extremum per (class, bin) every rank is 1, which is the common case,
+    // so the pairwise count runs only when two of them share a bin and class
+    const unsigned long long ext = lostm & (m_min | m_max);
+    int cnt = 0;
+    if (ext & (ext - 1)) {
+      const int ck = (q << 1) | (lane_in(m_max) ? 1 : 0);
+      unsigned shared = 0;
+      unsigned long long m = ext;
+      while (m) {
+        const unsigned long long grp = __ballot(ck == __builtin_amdgcn_readlane(ck, __ffsll((long long)m) - 1)) & ext;
+        m &= ~grp;
+        shared |= __popcll(grp) - 1;
+      }
+      if (shared) {
+        const int ok = lane_in(m_max) ? fkey(av) : -fkey(av);
+        unsigned long long mm = ext;
+        while (mm) {
+          const int j = __ffsll((long long)mm) - 1;
+          mm &= mm - 1;
+          const int ckj = __builtin_amdgcn_readlane(ck, j);
+          const int okj = __builtin_amdgcn_readlane(ok, j);
+          cnt += (ck == ckj && okj < ok) ? 1 : 0;
+        }
+      }
+    }
+    const int delta = (lane_in(lostm) ? 1 : 0) + (lane_in(ext) ? cnt : 0);
+    // B + LZ (residual i = v_i - v_{i-1}, residual 0 = 0) and BE of the bin
+    // indices (offset by 2^31 so that unsigned order is signed order) and of
+    // the ranks; one OR over the wave gives both widths (data below bit 24,
+    // ranks of at most 7 bits above)
+    const unsigned qb = (unsigned)q ^ 0x80000000u;
+    const unsigned pb = (unsigned)dpp_from_prev((int)qb, (int)qb);
+    const unsigned md = absdiff_u32(qb, pb);
+    const unsigned long long sign = __ballot(qb < pb);
+    const unsigned ud = (unsigned)delta;
+    const unsigned pr = (unsigned)dpp_from_prev((int)ud, (int)ud);
+    const unsigned mr = absdiff_u32(ud, pr);
+    const unsigned long long rsign = __ballot(ud < pr);
+    const unsigned o = wave_or(md | (mr << 24));
+    const unsigned od = o & 0xFFFFFFu, orr = o >> 24;
+    const int w = od ? 32 - __builtin_clz(od) : 0;
+    const int wr = orr ? 32 - __builtin_clz(orr) : 0;
+    put_planes<kMaxWData>(md, w, stg_d + (size_t)b * 2 * kMaxWData, lane);
+    put_planes<kMaxWRankBlk>(mr, wr, stg_r + (size_t)b * 2 * kMaxWRankBlk, lane);
+    // lane 0 holds the block's first value and first rank
+    if (lane == 0) {
+      wd_w[k] = w;
+      sign_w[k] = sign;
+      first_w[k] = q;
+      wr_w[k] = wr;
+      rsign_w[k] = rsign;
+      rfirst_w[k] = delta;
+    }
+    // 2-bit labels (Section IV-A (1)), 16 points per dword: bit 0 marks an
+    // extremum, bit 1 a saddle or maximum (m=01, s=10, M=11)
+    const unsigned lv = row_or_last((lane_in(m_min | m_max) ? lab_b0 : 0u) | (lane_in(m_sad | m_max) ? lab_b1 : 0u));
+    if ((lane & 15) == 15) lab_w[4 * k] = lv;
+    return true;
+  };
+
+  if (fast_mode) {
+    // the wave's blocks with four in flight; blocks that are not interior,
+    // those at an x boundary and those whose fast attempt fails are left in
+    // `todo` for a second pass (inlining the x-boundary case here measures
+    // slower: it costs registers and so occupancy)
+    constexpr int kDepth = 4;  // blocks in flight
+    unsigned todo = (1u << BPW) - 1u;
+    auto wave_loop = [&](auto fetch) {
+      EncIn P[kDepth];
+      unroll<0, kDepth>([&](auto kc) { P[kc.value] = fetch(kc.value); });
+      // (a barrier: each wave of the workgroup reaches it once, whichever
+      // version of this loop it runs)
+      get_bound();
+      unroll<0, BPW>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const EncIn& in = P[k % kDepth];
+        if ((fastm >> k) & 1ull) {
+          if (block_fast(in, kc, std::false_type{}, ~0ull, ~0ull)) todo &= ~(1u << k);
+        }
+        if constexpr (k + kDepth < BPW) P[k % kDepth] = fetch(k + kDepth);
+      });
+    };
+    if (inner)
+      wave_loop(fetch_inner);
+    else
+      wave_loop(fetch_clamped);
+    while (todo) {
+      const int k = __ffs((int)todo) - 1;
+      todo &= todo - 1;
+      const EncIn in = enc_fetch<ND>(f, bw + k, lane, g);
+      if ((xbm >> k) & 1ull) {
+        const int l0 = __builtin_amdgcn_readlane(l0v, k), l1 = __builtin_amdgcn_readlane(l1v, k);
+        const unsigned long long xm0 = l0 < kB ? ~(1ull << l0) : ~0ull, xm1 = l1 < kB ? ~(1ull << l1) : ~0ull;
+        if (block_fast(in, k, std::true_type{}, xm0, xm1)) continue;
+      }
+      block(in, bw + k);
+    }
+  } else {
+    // four blocks in flight per wave: each buffer is refilled as soon as its
+    // block has been encoded (the last refills repeat the wave's last block)
+    const int blast = bw + BPW - 1;
+    EncIn P0 = fetch_clamped(0), P1 = fetch_clamped(1), P2 = fetch_clamped(2), P3 = fetch_clamped(3);
+    get_bound();
+    for (int k = 0; k < BPW; k += 4) {
+      block(P0, bw + k);
+      P0 = enc_fetch<ND>(f, min(bw + k + 4, blast), lane, g);
+      block(P1, bw + k + 1);
+      P1 = enc_fetch<ND>(f, min(bw + k + 5, blast), lane, g);
+      block(P2, bw + k + 2);
+      P2 = enc_fetch<ND>(f, min(bw + k + 6, blast), lane, g);
+      block(P3, bw + k + 3);
+      P3 = enc_fetch<ND>(f, min(bw + k + 7, blast), lane, g);
+    }
   }
   if (MODE == kModeMark) {
     // one range of the compacted arrays per workgroup from the field-wide
@@ -920,81 +1214,55 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   }
   {
     const bool nf = nfm != 0, qo = qom != 0 || wover;
-    if (lane == 0 && (nf || qo)) atomicOr(&sh.flags, (nf ? 1u : 0u) | (qo ? 4u : 0u));
+    if (lane == 0) sh.wfl[wv] = wflag | (nf ? 1u : 0u) | (qo ? 4u : 0u);
+  }
+  // this wave's blocks' fixed-size parts, from its own LDS slots (written
+  // by lane 0 and by the label lanes above; the fences keep the reads after
+  // those writes): widths, signs and first values by lanes [0, BPW) for the
+  // data and [BPW, 2 BPW) for the ranks, then the labels, 4 dwords per block
+  uint8_t* out = a.out;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  {
+    const int k = lane % BPW, b = bw + k;
+    if (b < a.nb) {
+      if (lane < BPW) {
+        out[a.off[S2] + b] = (uint8_t)wd_w[k];
+        *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = sign_w[k];
+        *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = first_w[k];
+      } else if (lane < 2 * BPW && topo) {
+        out[a.off[R2] + b] = (uint8_t)wr_w[k];
+        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = rsign_w[k];
+        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = rfirst_w[k];
+      }
+    }
+    static_assert(4 * BPW <= 64, "one label dword per lane");
+    if (topo && lane < 4 * BPW && bw + (lane >> 2) < a.nb)
+      *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)bw + 4 * (size_t)lane) = sh.lab[4 * lb0 + lane];
   }
   __syncthreads();
 
-  // per-block fixed-size parts, coalesced: widths, signs, first values,
-  // labels, and the same for the ranks
-  uint8_t* out = a.out;
-  {
-    const int lb = tid & 63, part = tid >> 6;
-    const int b = c * kB + lb;
-    if (b < a.nb) {
-      if (part == 0) {
-        out[a.off[S2] + b] = (uint8_t)sh.wd[lb];
-        *reinterpret_cast<unsigned long long*>(out + a.off[S3] + 8 * (size_t)b) = sh.sign[lb];
-        *reinterpret_cast<int*>(out + a.off[S4] + 4 * (size_t)b) = sh.first[lb];
-      } else if (part == 1 && topo) {
-        out[a.off[R2] + b] = (uint8_t)sh.wr[lb];
-        *reinterpret_cast<unsigned long long*>(out + a.off[R3] + 8 * (size_t)b) = sh.rsign[lb];
-        *reinterpret_cast<int*>(out + a.off[R4] + 4 * (size_t)b) = sh.rfirst[lb];
-      }
-    }
-    // the chunk's labels: 4 dwords per block, one per thread of the first 256
-    if (topo && tid < kB * 4 && c * kB + (tid >> 2) < a.nb)
-      *reinterpret_cast<unsigned*>(out + a.off[S6] + 16 * (size_t)(c * kB) + 4 * (size_t)tid) = sh.lab[tid];
-  }
-
-  // chunk: constant-block bitmaps, local prefix of widths, chunk totals
-  const CompLayout L = comp_layout((uint64_t)a.nch, a.field);
+  // chunk: constant-block bitmaps and plane totals
   if (wv == 0) {
     const int b = c * kB + lane;
     const bool bv = b < a.nb;
     const int wd = sh.wd[lane], wr = sh.wr[lane];
     const unsigned long long cb = __ballot(bv && wd == 0), cr = __ballot(bv && wr == 0);
     const int sd = wave_incl_scan(wd, lane), sr = wave_incl_scan(wr, lane);
-    sh.pfd[lane + 1] = sd;
-    sh.pfr[lane + 1] = sr;
     if (lane == 0) {
-      sh.pfd[0] = 0;
-      sh.pfr[0] = 0;
       *reinterpret_cast<unsigned long long*>(out + a.off[S1] + 8 * (size_t)c) = cb;
       if (topo) *reinterpret_cast<unsigned long long*>(out + a.off[R1] + 8 * (size_t)c) = cr;
     }
     if (lane == 63) {
       reinterpret_cast<unsigned*>(a.ws + L.tot_d)[c] = (unsigned)sd;
       reinterpret_cast<unsigned*>(a.ws + L.tot_r)[c] = (unsigned)sr;
-      reinterpret_cast<unsigned*>(a.ws + L.cflag)[c] = sh.flags;
+      unsigned fl = 0;
+      for (int w = 0; w < WAVES; ++w) fl |= sh.wfl[w];
+      reinterpret_cast<unsigned*>(a.ws + L.cflag)[c] = fl;
     }
   }
-  __syncthreads();
 
-  // this chunk's planes, compact, to its staging slot (coalesced from LDS)
-  {
-    const int totd = 2 * sh.pfd[kB];
-    unsigned* dst = reinterpret_cast<unsigned*>(a.ws + L.stage_d) + (size_t)c * kB * 2 * kMaxWData;
-    for (int o = tid; o < totd; o += WAVES * 64) {
-      int lo = 0, hi = kB;  // find lb with 2 sh.pfd[lb] <= o < 2 sh.pfd[lb+1]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (2 * sh.pfd[mid] <= o) lo = mid; else hi = mid;
-      }
-      dst[o] = sh.pd[lo][o - 2 * sh.pfd[lo]];
-    }
-    if (topo) {
-      const int totr = 2 * sh.pfr[kB];
-      unsigned* rdst = reinterpret_cast<unsigned*>(a.ws + L.stage_r) + (size_t)c * kB * 2 * MAXWR;
-      for (int o = tid; o < totr; o += WAVES * 64) {
-        int lo = 0, hi = kB;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (2 * sh.pfr[mid] <= o) lo = mid; else hi = mid;
-        }
-        rdst[o] = sh.pr[lo][o - 2 * sh.pfr[lo]];
-      }
-    }
-  }
   // the last chunk zeroes the alignment gaps between the fixed-size parts
   if (c == a.nch - 1 && tid < 8 * (X2 + 1)) {
     const int s = tid >> 3, k = tid & 7;
@@ -1003,10 +1271,12 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   }
 }
 
-// At most 96 SGPRs: eight waves per SIMD instead of seven (a few values then
-// live in VGPR lanes), which measures about 4% faster.
+// At most 80 SGPRs and 64 VGPRs: eight waves per SIMD, so a CU holds four
+// eight-wave workgroups (measured: with 94 SGPRs it holds three, and the 3D
+// instance at 84 VGPRs two), at the cost of a few values kept in VGPR lanes.
 template <int ND, int WAVES, int MODE = kModeBlock>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_num_sgpr(96))) void encode_kernel(EncArgs a) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_num_sgpr(80), amdgpu_waves_per_eu(8, 8))) void
+encode_kernel(EncArgs a) {
   __shared__ EncSharedT<MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk> sh;
   const int c = xcd_chunk(blockIdx.x, a.nch);
   if (c < a.nch) encode_body<ND, WAVES, MODE>(a, c, sh);
@@ -1228,17 +1498,37 @@ __device__ __forceinline__ void finalize_body(const FinArgs& a, int c) {
   }
   if (!a.topo) totr = 0;
   {
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(a.ws + L.stage_d) + (size_t)c * kB * kMaxWData;
-    uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + b0;
-    for (uint64_t o = tid; o < nd; o += blockDim.x) dst[o] = src[o];
+    // each block's planes sit at the start of its staging slot: the chunk's
+    // widths (S2, R2, written by encode) give every block's position in the
+    // chunk's run; four threads copy each block
+    __shared__ int s_bd[kB + 1], s_br[kB + 1];
+    if (wv == 0) {
+      const uint64_t bb = (uint64_t)c * kB + lane;
+      const bool bv = bb < (uint64_t)a.nb;
+      const int wd = bv ? a.out[a.off[S2] + bb] : 0;
+      const int wr = (bv && a.topo) ? a.out[a.off[R2] + bb] : 0;
+      s_bd[lane + 1] = wave_incl_scan(wd, lane);
+      s_br[lane + 1] = wave_incl_scan(wr, lane);
+      if (lane == 0) {
+        s_bd[0] = 0;
+        s_br[0] = 0;
+      }
+    }
+    __syncthreads();
+    const int lb = tid >> 2, q4 = tid & 3;
+    const int rw = rank_w(a.field);
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(a.ws + L.stage_d) + ((size_t)c * kB + lb) * kMaxWData;
+    uint64_t* dst = reinterpret_cast<uint64_t*>(a.out + a.off[S5]) + b0 + s_bd[lb];
+    for (int j = q4; j < s_bd[lb + 1] - s_bd[lb]; j += 4) dst[j] = src[j];
     if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X1] + 8 * (size_t)c) = 8 * b0;
     if (a.topo) {
-      const uint64_t* rsrc =
-          reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + (size_t)c * kB * rank_w(a.field);
-      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.out + a.off[S5] + 8 * totd) + r0;
-      for (uint64_t o = tid; o < nr; o += blockDim.x) rdst[o] = rsrc[o];
+      const uint64_t* rsrc = reinterpret_cast<const uint64_t*>(a.ws + L.stage_r) + ((size_t)c * kB + lb) * rw;
+      uint64_t* rdst = reinterpret_cast<uint64_t*>(a.out + a.off[S5] + 8 * totd) + r0 + s_br[lb];
+      for (int j = q4; j < s_br[lb + 1] - s_br[lb]; j += 4) rdst[j] = rsrc[j];
       if (tid == 0) *reinterpret_cast<uint64_t*>(a.out + a.off[X2] + 8 * (size_t)c) = 8 * r0;
     }
+    (void)nd;
+    (void)nr;
   }
   if (!head) return;
   __syncthreads();
