@@ -1626,24 +1626,26 @@ struct Hdr {
   uint64_t off[kNSeg], len[kNSeg];
 };
 
-template <typename T>
-__device__ __forceinline__ T rd(const uint8_t* p, int off) {
-  T v;
-  memcpy(&v, p + off, sizeof(T));
-  return v;
-}
 
 // Header checks (one wave): the header is copied to LDS in parallel, then
 // lane 0 checks the checksum, field ranges and the segment table against the
 // layout rule.  Result in *h: ok = 0 corrupt, -1 capacity, 1 good.
+// Lane l's 8 header bytes [8l, 8l + 8), read from any lane.
+__device__ __forceinline__ uint64_t hdr_word(uint64_t w, int l) {
+  return (uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)w, l) |
+         (uint64_t)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(w >> 32), l) << 32;
+}
+
+// Parses and checks the 512-byte header (one wave; lane 0 writes *h).  Each
+// lane loads 8 bytes; every field is then read from the lanes' registers, so
+// the checks wait on no memory.
 __device__ __forceinline__ void parse_header(const uint8_t* in, uint64_t in_size, uint64_t out_cap, Hdr* h,
-                             uint8_t* hb, int lane) {
+                                             int lane) {
   const bool good = in_size >= (uint64_t)kHdr;
   unsigned sa = 0, sb = 0;
+  uint64_t w = 0;
   if (good) {
-    // 512 header bytes: 8 per lane
-    const uint64_t w = *reinterpret_cast<const uint64_t*>(in + 8 * lane);
-    *reinterpret_cast<uint64_t*>(hb + 8 * lane) = w;
+    w = *reinterpret_cast<const uint64_t*>(in + 8 * lane);
     for (int j = 0; j < 8; ++j) {
       const int i = 8 * lane + j;
       const unsigned b = (unsigned)((w >> (8 * j)) & 0xFFu);
@@ -1658,54 +1660,58 @@ __device__ __forceinline__ void parse_header(const uint8_t* in, uint64_t in_size
     sa += (unsigned)__shfl_xor((int)sa, o);
     sb += (unsigned)__shfl_xor((int)sb, o);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane != 0) return;
   h->ok = 0;
   if (!good) return;
-  const uint32_t adler = (uint32_t)((((uint64_t)kSummed + sb) % 65521u) << 16 | ((1ull + sa) % 65521u));
-  if (hb[0] != 'T' || hb[1] != 'S' || hb[2] != 'Z' || hb[3] != '1') return;
-  if (rd<uint16_t>(hb, 4) != 1) return;
-  if (rd<uint32_t>(hb, kSummed) != adler || rd<uint32_t>(hb, kSummed + 4) != 0) return;
-  h->ndim = hb[6];
+  // Adler-32 of bytes [0, kSummed): sa <= 376 * 255 and sb < 2^25, so 32 bits hold both sums
+  const uint32_t adler = (((unsigned)kSummed + sb) % 65521u) << 16 | ((1u + sa) % 65521u);
+  const uint64_t w0 = hdr_word(w, 0);
+  if ((uint32_t)w0 != 0x315A5354u) return;  // "TSZ1"
+  if (((w0 >> 32) & 0xFFFFu) != 1) return;
+  const uint64_t w47 = hdr_word(w, kSummed / 8);
+  if ((uint32_t)w47 != adler || (uint32_t)(w47 >> 32) != 0) return;
+  h->ndim = (int)((w0 >> 48) & 0xFFu);
   if (h->ndim != 2 && h->ndim != 3) return;
-  if (hb[7] & ~3u) return;
-  h->topo = hb[7] & 1;
-  h->scope = (hb[7] >> 1) & 1;
+  const unsigned flags = (unsigned)(w0 >> 56);
+  if (flags & ~3u) return;
+  h->topo = flags & 1;
+  h->scope = (flags >> 1) & 1;
   uint64_t prod = 1;
   for (int d = 0; d < 3; ++d) {
-    h->dims[d] = rd<uint64_t>(hb, 8 + 8 * d);
+    h->dims[d] = hdr_word(w, 1 + d);
     if (h->dims[d] < 1 || h->dims[d] > (1ull << 31)) return;
     if (d >= h->ndim && h->dims[d] != 1) return;
     prod *= h->dims[d];
     if (prod >= (1ull << 31)) return;
   }
-  h->n = rd<uint64_t>(hb, 32);
-  h->nb = rd<uint64_t>(hb, 40);
-  h->nch = rd<uint64_t>(hb, 152);
+  h->n = hdr_word(w, 4);
+  h->nb = hdr_word(w, 5);
+  h->nch = hdr_word(w, 19);
   if (h->n != prod || h->nb != (h->n + kB - 1) / kB || h->nch != (h->nb + kB - 1) / kB) return;
-  if (rd<uint32_t>(hb, 48) != (uint32_t)kB) return;
-  h->k = hb[53];
-  h->max_rounds = rd<uint16_t>(hb, 54);
-  if (hb[52] > 1 || (h->k != 3 && h->k != 5 && h->k != 7) || h->max_rounds < 1) return;
-  h->e = rd<float>(hb, 72);
+  const uint64_t w6 = hdr_word(w, 6);  // block (48), eb mode (52), k (53), rounds (54)
+  if ((uint32_t)w6 != (uint32_t)kB) return;
+  h->k = (int)((w6 >> 40) & 0xFFu);
+  h->max_rounds = (int)(w6 >> 48);
+  if (((w6 >> 32) & 0xFFu) > 1 || (h->k != 3 && h->k != 5 && h->k != 7) || h->max_rounds < 1) return;
+  h->e = __uint_as_float((unsigned)hdr_word(w, 9));  // byte 72
   if (!(h->e >= 0x1p-100f) || !(h->e <= 0x1p100f)) return;
-  for (int d2 = 0; d2 < 10; ++d2) {
-    h->w[d2] = rd<float>(hb, 88 + 4 * d2);
-    if (!(h->w[d2] > 0.0f) || !(h->w[d2] <= 1.0f)) return;
+  for (int d2 = 0; d2 < 10; d2 += 2) {
+    const uint64_t wk = hdr_word(w, 11 + d2 / 2);  // bytes 88 + 4 d2
+    h->w[d2] = __uint_as_float((unsigned)wk);
+    h->w[d2 + 1] = __uint_as_float((unsigned)(wk >> 32));
+    if (!(h->w[d2] > 0.0f) || !(h->w[d2] <= 1.0f) || !(h->w[d2 + 1] > 0.0f) || !(h->w[d2 + 1] <= 1.0f)) return;
   }
-  h->total = rd<uint64_t>(hb, 128);
-  h->wdata = rd<uint64_t>(hb, 136);
-  h->wrank = rd<uint64_t>(hb, 144);
+  h->total = hdr_word(w, 16);
+  h->wdata = hdr_word(w, 17);
+  h->wrank = hdr_word(w, 18);
   if (h->wdata > h->nb * kMaxWData || h->wrank > h->nb * kMaxWRankAny) return;
   uint64_t off[kNSeg], len[kNSeg];
   const uint64_t total = seg_layout(h->nb, h->topo, h->wdata, h->wrank, off, len);
   if (total != h->total || total > in_size) return;
-  for (int s = 0; s < kNSeg; ++s) {
-    h->off[s] = rd<uint64_t>(hb, 160 + 8 * s);
-    h->len[s] = rd<uint64_t>(hb, 264 + 8 * s);
-    if (h->off[s] != off[s] || h->len[s] != len[s]) return;
+  for (int sg = 0; sg < kNSeg; ++sg) {
+    h->off[sg] = hdr_word(w, 20 + sg);  // bytes 160 + 8 s
+    h->len[sg] = hdr_word(w, 33 + sg);  // bytes 264 + 8 s
+    if (h->off[sg] != off[sg] || h->len[sg] != len[sg]) return;
   }
   h->ok = (h->n <= out_cap) ? 1 : -1;
 }
@@ -1717,22 +1723,19 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
   constexpr int BPW = kB / WAVES;
   constexpr int kRankLds = kB * kMaxWRankBlk;  // rank planes staged when they fit
   __shared__ Hdr s_h;
-  __shared__ uint64_t s_hb[kHdr / 8];
   __shared__ unsigned long long s_pl[kB * kMaxWData], s_rpl[kRankLds];
   __shared__ unsigned long long s_sign[kB], s_rsign[kB], s_bm[kB];
   __shared__ int s_first[kB], s_rfirst[kB];
   __shared__ unsigned s_lab[kB * 4];
   __shared__ int s_pfd[kB + 1], s_pfr[kB + 1], s_wd[kB], s_wr[kB];
-  __shared__ unsigned long long s_xd, s_xr;
   __shared__ int s_bad;
-  __shared__ unsigned s_qn, s_moves, s_skips, s_corrupt;
+  __shared__ unsigned s_moves, s_skips, s_corrupt;
   Ctrl* ct = ctrl_of(a.ws);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, reinterpret_cast<uint8_t*>(s_hb), lane);
+  if (wv == 0) parse_header(a.in, a.in_size, a.out_cap, &s_h, lane);
   if (tid == 0) {
     s_bad = 0;
-    s_qn = 0;
     s_moves = 0;
     s_skips = 0;
     s_corrupt = 0;
@@ -1797,8 +1800,33 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
   const int n = (int)h.n;
   const bool topo = h.topo != 0;
 
-  // the chunk's fixed-size parts to LDS (every thread), and its widths,
-  // constant flags and payload offsets (wave 0)
+  // The chunk's payload ranges (X1, X2), read by every wave: each wave starts
+  // its share of the plane copy to LDS at once, bounds-checked against the
+  // segment, while wave 0 checks the ranges against the widths below.
+  const uint64_t* x1 = reinterpret_cast<const uint64_t*>(a.in + h.off[X1]);
+  const uint64_t xd = x1[c], nxd = (uint64_t)c + 1 < h.nch ? x1[c + 1] : h.len[S5];
+  uint64_t xr = 0, nxr = 0;
+  if (topo) {
+    const uint64_t* x2 = reinterpret_cast<const uint64_t*>(a.in + h.off[X2]);
+    xr = x2[c];
+    nxr = (uint64_t)c + 1 < h.nch ? x2[c + 1] : h.len[R5];
+  }
+  const bool dfit = xd <= nxd && nxd <= h.len[S5] && nxd - xd <= 8ull * kB * kMaxWData;
+  const bool rank_lds = topo && xr <= nxr && nxr <= h.len[R5] && nxr - xr <= 8ull * kRankLds;
+  {
+    if (dfit) {
+      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(a.in + h.off[S5] + (xd & ~7ull));
+      const int nd = (int)((nxd - xd) >> 3);
+      for (int o = tid; o < nd; o += WAVES * 64) s_pl[o] = src[o];
+    }
+    if (rank_lds) {
+      const unsigned long long* rsrc = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + (xr & ~7ull));
+      const int nr = (int)((nxr - xr) >> 3);
+      for (int o = tid; o < nr; o += WAVES * 64) s_rpl[o] = rsrc[o];
+    }
+  }
+  // the chunk's fixed-size parts to LDS (every thread), and its widths and
+  // constant flags (wave 0)
   {
     const int lb = tid & 63, part = tid >> 6;
     const uint64_t b = (uint64_t)c * kB + lb;
@@ -1837,23 +1865,13 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     if (lane == 0) {
       s_pfd[0] = 0;
       s_pfr[0] = 0;
+      // the payload ranges must be exactly the chunk's planes (the copy
+      // above then holds them all)
       const uint64_t totd = 8ull * (unsigned)__builtin_amdgcn_readlane(sd, 63);
       const uint64_t totr = 8ull * (unsigned)__builtin_amdgcn_readlane(sr, 63);
-      const uint64_t xd = *reinterpret_cast<const uint64_t*>(a.in + h.off[X1] + 8 * (uint64_t)c);
-      const uint64_t nxd = (uint64_t)c + 1 < h.nch
-                               ? *reinterpret_cast<const uint64_t*>(a.in + h.off[X1] + 8 * ((uint64_t)c + 1))
-                               : h.len[S5];
       bool b2 = anybad || (c == 0 && xd != 0) || xd > h.len[S5] || totd > h.len[S5] - xd || xd + totd != nxd;
-      uint64_t xr = 0;
-      if (topo) {
-        xr = *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * (uint64_t)c);
-        const uint64_t nxr = (uint64_t)c + 1 < h.nch
-                                 ? *reinterpret_cast<const uint64_t*>(a.in + h.off[X2] + 8 * ((uint64_t)c + 1))
-                                 : h.len[R5];
+      if (topo)
         b2 = b2 || (c == 0 && xr != 0) || xr > h.len[R5] || totr > h.len[R5] - xr || xr + totr != nxr;
-      }
-      s_xd = xd;
-      s_xr = xr;
       s_bad = b2 ? 1 : 0;
     }
   }
@@ -1874,42 +1892,36 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     return;
   }
 
-  // the chunk's bit planes to LDS (coalesced); rank planes too when they fit
-  const int nd = s_pfd[kB], nr = s_pfr[kB];
-  const bool rank_lds = nr <= kRankLds;
-  {
-    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(a.in + h.off[S5] + s_xd);
-    for (int o = tid; o < nd; o += WAVES * 64) s_pl[o] = src[o];
-    if (topo && rank_lds) {
-      const unsigned long long* rsrc = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + s_xr);
-      for (int o = tid; o < nr; o += WAVES * 64) s_rpl[o] = rsrc[o];
-    }
-  }
-  __syncthreads();
-
   const double ed = (double)h.e;
   const float two_e = 2.0f * h.e;
   const int dmax = h.scope ? n : kB;
-  const unsigned long long* rglob = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + s_xr);
+  const unsigned long long* rglob = reinterpret_cast<const unsigned long long*>(a.in + h.off[R5] + xr);
   unsigned* qi = reinterpret_cast<unsigned*>(a.ws + L.idx) + (size_t)c * kChunk;
-  bool corrupt = false;
+  // wave-uniform tallies: lanes that read corrupt, stencil moves and skips
+  unsigned long long corrupt_m = 0;
   unsigned moves = 0, skips = 0;
-  // one block's work once its values (q) and ranks (dl) are decoded
+  const unsigned lsh = 2u * ((unsigned)lane & 15u);  // this lane's label bits in its dword
+  // one block's work once its values (q) and ranks (dl) are decoded; the
+  // per-point decisions are wave masks, so no lane branches
   auto finish = [&](int lb, int q, int dl) {
-    const uint64_t b = (uint64_t)c * kB + lb;
-    const int i = (int)(b * kB) + lane;
-    const bool valid = i < n;
-    corrupt |= valid && (q > kQMax || q < -kQMax);
+    const int i0 = (c * kB + lb) * kB;  // the block's first point (n < 2^31)
+    const int nv = n - i0;              // points of the block inside the field
+    const unsigned long long vm = nv >= kB ? ~0ull : ((1ull << nv) - 1ull);
+    // |q| <= kQMax, as one unsigned compare
+    corrupt_m |= __ballot((unsigned)q + (unsigned)kQMax > 2u * (unsigned)kQMax) & vm;
     const float rq = (float)q * two_e;  // float(2q) * e: the same exact product
     float v = rq;
-    bool queue = false;
     if (topo) {
-      corrupt |= valid && (dl < 0 || dl > dmax);
+      corrupt_m |= __ballot((unsigned)dl > (unsigned)dmax) & vm;  // dl < 0 reads as large
       const unsigned lw = s_lab[4 * lb + (lane >> 4)];
-      const int lab = valid ? (int)((lw >> (2 * (lane & 15))) & 3u) : CLS_R;
-      if (valid && dl > 0 && (lab == CLS_MIN || lab == CLS_MAX)) {
-        // flattened extremum: its neighbour maximum (minimum) is its own bin
-        // centre, so the stencil value is delta float steps beyond it
+      // label bit 0 marks an extremum, bit 1 a saddle or a maximum
+      const unsigned long long b0 = __ballot((lw >> lsh) & 1u), b1 = __ballot((lw >> lsh) & 2u);
+      const unsigned long long pos = __ballot(dl > 0) & vm;
+      const unsigned long long mv = pos & b0;  // flattened extrema
+      if (mv) {
+        // the extremum's neighbour maximum (minimum) is its own bin centre,
+        // so its stencil value is delta float steps beyond it
+        const unsigned sd = lane_in(b1) ? (unsigned)dl : 0u - (unsigned)dl;
         float cand;
         bool fits;
         if (h.scope == 0) {
@@ -1920,32 +1932,22 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
           // candidate keeps the centre's sign and lies within a factor 2 of
           // it, so their float difference is exact (Sterbenz) and the budget
           // test needs no double
-          const int kk = (int)((unsigned)fkey(rq) + (unsigned)(lab == CLS_MAX ? dl : -dl));
-          cand = key2f32(kk);
+          cand = key2f32((int)((unsigned)fkey(rq) + sd));
           fits = fabsf(cand - rq) <= h.e;
         } else {
-          const long long kk = (long long)fkey(rq) + (lab == CLS_MAX ? (long long)dl : -(long long)dl);
-          cand = key2f(kk);
+          cand = key2f((long long)fkey(rq) + (long long)(int)sd);
           fits = fabs((double)cand - (double)rq) <= ed;
         }
-        if (fits) {
-          v = cand;
-          ++moves;
-        } else {
-          ++skips;
-        }
+        const unsigned long long fm = __ballot(fits) & mv;
+        v = lane_in(fm) ? cand : rq;
+        moves += (unsigned)__popcll(fm);
+        skips += (unsigned)__popcll(mv & ~fm);
       }
-      queue = valid && dl > 0 && lab == CLS_SAD;
-      const unsigned long long qm = __ballot(queue);
-      if (lane == 0) s_bm[lb] = qm;
-      if (qm) {
-        unsigned base = 0;
-        if (lane == 0) base = atomicAdd(&s_qn, (unsigned)__popcll(qm));
-        base = (unsigned)__builtin_amdgcn_readlane((int)base, 0);
-        if (queue) qi[base + mbcnt(qm)] = (unsigned)i;
-      }
+      // flattened saddles: queued (their indices go out after the barrier)
+      if (lane == 0) s_bm[lb] = pos & b1 & ~b0;
     }
-    if (valid) a.out[i] = v;
+    float* const ob = a.out + i0;
+    if (lane_in(vm)) ob[lane] = v;
   };
   // blocks two at a time (BPW is even): the pair's plane reads and prefix
   // sums interleave; a pair past the end of the field keeps its first block
@@ -1960,7 +1962,12 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
                 s_first[lb + 1], s_sign[lb + 1], lane, q0, q1);
     if (topo) {
       const int wr1 = two ? s_wr[lb + 1] : 0;
-      if (rank_lds)
+      if (s_wr[lb] == 0 && wr1 == 0) {
+        // two constant rank blocks (the common case away from flattened
+        // points): every rank is the block's first
+        d0 = s_rfirst[lb];
+        d1 = s_rfirst[lb + 1];
+      } else if (rank_lds)
         decode_pair(s_rpl + s_pfr[lb], s_wr[lb], s_rfirst[lb], s_rsign[lb], s_rpl + s_pfr[lb + 1], wr1,
                     s_rfirst[lb + 1], s_rsign[lb + 1], lane, d0, d1);
       else
@@ -1970,18 +1977,31 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     finish(lb, q0, d0);
     if (two) finish(lb + 1, q1, d1);
   }
-  const bool cb = __ballot(corrupt) != 0;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    moves += (unsigned)__shfl_xor((int)moves, o);
-    skips += (unsigned)__shfl_xor((int)skips, o);
-  }
   if (lane == 0) {
     if (moves) atomicAdd(&s_moves, moves);
     if (skips) atomicAdd(&s_skips, skips);
-    if (cb) atomicOr(&s_corrupt, 1u);
+    if (corrupt_m) atomicOr(&s_corrupt, 1u);
   }
   __syncthreads();
+  // the chunk's queue of flattened saddles, in block order: each wave writes
+  // its own blocks' entries at offsets scanned from the queued-saddle bitmap
+  unsigned qtot = 0;
+  if (topo) {
+    const unsigned long long mine = (uint64_t)c * kB + lane < h.nb ? s_bm[lane] : 0ull;
+    const int pc = __popcll(mine);
+    const int incl = wave_incl_scan(pc, lane);
+    qtot = (unsigned)__builtin_amdgcn_readlane(incl, 63);
+    for (int k = 0; k < BPW; ++k) {
+      const int lb = wv * BPW + k;
+      const unsigned long long qm =
+          (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)mine, lb) |
+          ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(mine >> 32), lb) << 32);
+      if (qm) {
+        const unsigned off = (unsigned)__builtin_amdgcn_readlane(incl - pc, lb);
+        if (lane_in(qm)) qi[off + mbcnt(qm)] = (unsigned)((c * kB + lb) * kB + lane);
+      }
+    }
+  }
   // the chunk's queued-saddle bitmap (and a cleared word of the capped
   // bitmap beside each), and counters
   if (tid < kB && (uint64_t)c * kB + tid < h.nb) {
@@ -1989,7 +2009,7 @@ __device__ __forceinline__ void decode_body(const DecArgs& a, int w_id) {
     reinterpret_cast<unsigned long long*>(a.ws + L.capped)[(uint64_t)c * kB + tid] = 0;
   }
   if (tid == 0) {
-    reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = s_qn;
+    reinterpret_cast<unsigned*>(a.ws + L.cnt)[c] = qtot;
     reinterpret_cast<unsigned*>(a.ws + L.moves)[c] = s_moves;
     reinterpret_cast<unsigned*>(a.ws + L.skips)[c] = s_skips;
     dflag[c] = s_corrupt;
