@@ -39,11 +39,11 @@ def _src_hash():
     return h.hexdigest()
 
 
-def _counters(kernel):
-    """The committed rocprofv3 counter summary of `kernel` on this workload
-    (HBM bytes per launch, VALU/SALU instructions), if it was taken on the
-    current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_1800x3600_rel1e-3.json" % kernel)
+def _counters(kernel, tag="1800x3600_rel1e-3"):
+    """The committed rocprofv3 counter summary of `kernel` on the workload
+    `tag` (HBM bytes per launch, VALU/SALU instructions), if it was taken on
+    the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, tag))
     if not os.path.exists(path):
         return None
     try:
@@ -53,6 +53,26 @@ def _counters(kernel):
     if d.get("source_sha256") != _src_hash():
         return None
     return d
+
+
+def roofline_of(kernel, alg_bytes, ms, n, tag="1800x3600_rel1e-3"):
+    """The HBM roofline entry of one kernel: algorithmic bytes per launch over
+    its average launch time (HIP events on the call's stream), the counter
+    traffic of the committed profile when it matches the source, and the
+    VALU issue rate from the same profile."""
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    cnt = _counters(kernel, tag)
+    out = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+           "traffic": cnt["bytes_per_launch"] if cnt else None, "alg_bytes": alg_bytes,
+           "ms": round(ms, 5)}
+    if cnt and cnt.get("valu_per_launch"):
+        ops = cnt["valu_per_launch"] * 64
+        out["valu"] = {"lane_ops_per_elem": round(ops / n, 1),
+                       "achieved": round(ops / (ms * 1e-3) / 1e12, 2), "peak": VALU_PEAK_TOPS,
+                       "unit": "T lane-ops/s", "frac": round(ops / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+                       "salu_per_launch": cnt.get("salu_per_launch")}
+    return out
 
 
 def cpu_baseline(field, eb, target_s=10.0):
@@ -123,7 +143,9 @@ def cpu_all_cores(field, eb, s_ref, rec_ref, max_threads=16):
         same = list(ex.map(one, range(nt)))
         wall = time.perf_counter() - t0
     return {"value": round(field.nbytes * nt / wall / 1e9, 4), "unit": "GB/s", "threads": nt,
-            "sample": "%d concurrent whole-field round trips, %.2f s wall" % (nt, wall),
+            "kind": "throughput",
+            "sample": "%d independent whole-field round trips at once, one per thread (aggregate "
+                      "throughput, not one field split over the cores), %.2f s wall" % (nt, wall),
             "identical": all(same)}
 
 
@@ -197,7 +219,7 @@ def batch_leg(tsz, torch, dev, reps=20):
             "batched_equals_one_field": bool(same)}, fields, ebs, streams
 
 
-def workload_leg(tsz, torch, dev, field, eb, reps=40):
+def workload_leg(tsz, torch, dev, field, eb, reps=40, tag=None):
     """One-field compress and decompress of another workload: GB/s per call
     (rotated copies, inputs resident), ratio and topology counts."""
     R = 4
@@ -230,21 +252,50 @@ def workload_leg(tsz, torch, dev, field, eb, reps=40):
     ok = int(cst.item()) == 0 and int(dst.item()) == 0
     ev = tsz.eval_topology(ins[0], recs[0])
     nbytes = field.nbytes
-    return {"shape": list(shape), "eb": eb, "eb_mode": "rel",
-            "compress_gbps": round(nbytes / (ms_c * 1e-3) / 1e9, 2),
-            "decompress_gbps": round(nbytes / (ms_d * 1e-3) / 1e9, 2),
-            "compress_ms": round(ms_c, 5), "decompress_ms": round(ms_d, 5),
-            "ratio": round(nbytes / sl[0], 3), "status_ok": ok,
-            "missed_cps": {"FN": ev["FN"], "FP": ev["FP"], "FT": ev["FT"]}}
+    out = {"shape": list(shape), "eb": eb, "eb_mode": "rel",
+           "compress_gbps": round(nbytes / (ms_c * 1e-3) / 1e9, 2),
+           "decompress_gbps": round(nbytes / (ms_d * 1e-3) / 1e9, 2),
+           "compress_ms": round(ms_c, 5), "decompress_ms": round(ms_d, 5),
+           "ratio": round(nbytes / sl[0], 3), "status_ok": ok,
+           "missed_cps": {"FN": ev["FN"], "FP": ev["FP"], "FT": ev["FT"]}}
+    if tag is not None:
+        # per-kernel durations (HIP events on the call's stream) and the HBM
+        # roofline of encode and decode
+        kms = kernel_ms(tsz, torch, lambda k: (tsz.compress_async(ins[k], eb, "rel", ws=ws, out=outs[k],
+                                                                  size=sizes[k], status=cst),
+                                               tsz.decompress_async(outs[k], sl[k], recs[k], ws=ws, status=dst)),
+                        R, min(reps, 40))
+        n = field.size
+        out["kernels_ms"] = {k: round(v, 5) for k, v in kms.items()}
+        out["rooflines"] = {"encode": roofline_of("encode", 4 * n + sl[0], kms["encode"], n, tag),
+                            "decode": roofline_of("decode", sl[0] + 4 * n, kms["decode"], n, tag)}
+    return out
 
 
-def serve_leg(tsz, torch, fields, ebs, streams, seconds):
-    """Poisson arrivals (200 req/s, 70/30 compress/decompress) of requests on
-    the batch's fields and streams, served with continuous batching under a
-    64 GB admission limit."""
+def kernel_ms(tsz, torch, step, R, reps):
+    """Average duration (ms) of each library kernel over `reps` steps, from
+    the HIP events the library records around its kernels on the call's
+    stream."""
+    names = ["range", "encode", "finalize", "decode", "refine"]
+    acc = {k: 0.0 for k in names}
+    tsz.set_timing(True)
+    for i in range(reps):
+        step(i % R)
+        torch.cuda.synchronize()
+        t = tsz.kernel_times()
+        for k in names:
+            acc[k] += max(t[k], 0.0)
+    tsz.set_timing(False)
+    return {k: acc[k] / reps for k in names}
+
+
+def serve_leg(tsz, torch, fields, ebs, streams, seconds, rate=200.0, seed=4):
+    """Poisson arrivals (`rate` req/s, 70/30 compress/decompress) of requests
+    on the batch's fields and streams, served with continuous batching under
+    a 64 GB admission limit."""
     import numpy as np
     from paper_2602_17552_amd import datagen, serve
-    trace = datagen.serve_trace(rate=200.0, duration=seconds, frac_compress=0.7, seed=4)
+    trace = datagen.serve_trace(rate=rate, duration=seconds, frac_compress=0.7, seed=seed)
     rng = np.random.default_rng(8)
 
     def make(i, t, op):
@@ -257,11 +308,24 @@ def serve_leg(tsz, torch, fields, ebs, streams, seconds):
     reqs = serve.run_trace(srv, trace, make, realtime=True, deadline=seconds + 120.0)
     st = srv.stats()
     span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
-    st.update({"trace": "Poisson 200 req/s, %g s, 70/30 compress/decompress, fields of the batch" % seconds,
+    st.update({"trace": "Poisson %g req/s, %g s, 70/30 compress/decompress, fields of the batch" % (rate, seconds),
+               "rate_rps": rate,
                "sustained_gbps": round(sum(r.nbytes for r in reqs) / span / 1e9, 4),
                "offered_gbps": round(sum(r.nbytes for r in reqs) / seconds / 1e9, 4),
                "admission_limit_bytes": 64 << 30})
     return st
+
+
+def serve_sweep(tsz, torch, fields, ebs, streams, rates=(1000.0, 4000.0, 16000.0, 64000.0), seconds=2.0):
+    """The served form at rising Poisson rates: latency, batch size and
+    sustained GB/s at each, to find where continuous batching takes over
+    (mean batch > 1) and where the device saturates."""
+    out = []
+    for k, r in enumerate(rates):
+        st = serve_leg(tsz, torch, fields, ebs, streams, seconds, rate=r, seed=40 + k)
+        out.append({x: st[x] for x in ("rate_rps", "requests", "p50_ms", "p99_ms", "mean_batch", "max_batch",
+                                       "peak_inflight_batches", "sustained_gbps", "offered_gbps", "failed")})
+    return out
 
 
 def main():
@@ -274,8 +338,10 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="a few steps only (for profiler runs), no JSON line")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
-                    help="length of the served-form trace (0 skips it; 60 is the full configuration)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the served-form trace at 200 req/s (0 skips it and the rate sweep)")
+    ap.add_argument("--probe-workload", choices=["1800x3600", "256x256x256"], default="1800x3600",
+                    help="with --probe: the field the probe steps run on")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -289,19 +355,20 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
-    field = datagen.cfg1()
+    field = datagen.cfg2() if (args.probe and args.probe_workload == "256x256x256") else datagen.cfg1()
+    shape = tuple(field.shape)
     n = field.size
     nbytes = field.nbytes
-    R = max(1, args.copies)
+    R = max(1, args.copies) if shape == SHAPE else 4
     base = torch.from_numpy(field).to(dev)
     ins = [base.clone() for _ in range(R)]
-    cap = tsz.compress_bound(SHAPE)
+    cap = tsz.compress_bound(shape)
     outs = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in range(R)]
-    recs = [torch.empty(SHAPE, dtype=torch.float32, device=dev) for _ in range(R)]
+    recs = [torch.empty(shape, dtype=torch.float32, device=dev) for _ in range(R)]
     sizes = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(R)]
     cst = torch.zeros(1, dtype=torch.int32, device=dev)
     dst = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws = tsz.Workspace(SHAPE, dev)
+    ws = tsz.Workspace(shape, dev)
     stream = torch.cuda.current_stream()
 
     def comp(k):
@@ -371,18 +438,8 @@ def main():
 
     # per-kernel durations: HIP events recorded by the library around each of
     # its kernels, on the call's stream
-    tsz.set_timing(True)
     names = ["range", "encode", "finalize", "decode", "refine"]
-    acc = {k: 0.0 for k in names}
-    kreps = min(args.steps, 40)
-    for i in range(kreps):
-        step(i % R)
-        torch.cuda.synchronize()
-        t = tsz.kernel_times()
-        for k in names:
-            acc[k] += max(t[k], 0.0)
-    tsz.set_timing(False)
-    kms = {k: acc[k] / kreps for k in names}
+    kms = kernel_ms(tsz, torch, step, R, min(args.steps, 40))
 
     # topology counts and the largest error (the library's GPU evaluator);
     # parity against the oracle's stream and reconstruction comes from the
@@ -423,7 +480,8 @@ def main():
     # field and the 256^3 Gaussian random field, relative bound 1e-3
     others_wl = {
         "512x512 gaussian bumps + N(0,1e-3^2), seed 0": workload_leg(tsz, torch, dev, datagen.cfg0(), 1e-3),
-        "256^3 GRF |k|^-5/3 in [0,1], seed 2": workload_leg(tsz, torch, dev, datagen.cfg2(), 1e-3),
+        "256^3 GRF |k|^-5/3 in [0,1], seed 2": workload_leg(tsz, torch, dev, datagen.cfg2(), 1e-3,
+                                                             tag="256x256x256_rel1e-3"),
     }
 
     # field-scope ranks (the paper's whole-field reading of the rank set) on
@@ -453,6 +511,7 @@ def main():
         batched, bf, be, bs = batch_leg(tsz, torch, dev)
         if args.serve_seconds > 0:
             served = serve_leg(tsz, torch, bf, be, bs, args.serve_seconds)
+            served["rate_sweep"] = serve_sweep(tsz, torch, bf, be, bs)
         del bf, bs
 
     S = slen[0]
@@ -464,18 +523,12 @@ def main():
     kernels = {k: {"ms": round(kms[k], 5),
                    "GBps": round(alg[k] / (kms[k] * 1e-3) / 1e9, 1) if k in alg and kms[k] > 0 else None}
                for k in names}
-    cnt = _counters(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": cnt["bytes_per_launch"] if cnt else None,
-                "alg_bytes": alg[dom]}
-    valu = None
-    if cnt and cnt.get("valu_per_launch"):
-        ops = cnt["valu_per_launch"] * 64
-        valu = {"kernel": dom, "lane_ops_per_elem": round(ops / n, 1),
-                "achieved": round(ops / (kms[dom] * 1e-3) / 1e12, 2), "peak": VALU_PEAK_TOPS,
-                "unit": "T lane-ops/s", "frac": round(ops / (kms[dom] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
-                "salu_per_launch": cnt.get("salu_per_launch")}
+    rl = {k: roofline_of(k, alg[k], kms[k], n) for k in ("encode", "decode")}
+    roofline = dict(rl[dom]) if dom in rl else roofline_of(dom, alg[dom], kms[dom], n)
+    valu = roofline.pop("valu", None)
+    if valu is not None:
+        valu = dict(valu, kernel=dom)
+    roofline.pop("ms", None)
     value = nbytes / (ms_step * 1e-3) / 1e9
     line = {
         "metric": "compress/decompress GB/s at rel eb 1e-3; missed CPs; serve p50/p99 latency",
@@ -506,6 +559,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "valu": valu,
+        "rooflines": rl,
         "other_bounds": other,
         "other_workloads": others_wl,
         "field_scope_ranks": field_scope,

@@ -19,8 +19,7 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls are stream-ordered and asynchronous: results are valid once the
  *    stream has been synchronised.  Nothing is read back to the host except
- *    where a call says so (field-scope compression, the stats calls, the
- *    autotuners).
+ *    where a call says so (the stats calls, the autotuners).
  *  - The return value is a status: TOPOSZP_OK (0) or a negative error from
  *    the list below, detected on the host before anything is enqueued.
  *    Errors that only the device can see (non-finite input, values out of
@@ -63,9 +62,9 @@ typedef struct {
   uint32_t block;     /* points per block; must be 64 (default 64) */
   int32_t rank_scope; /* 0 = ranks among flattened extrema of the same 64-point
                          block (default); 1 = whole field (needs the _ex sizes;
-                         the call waits once on `stream` for the count of
-                         flattened extrema before it sorts them, so it returns
-                         after the preceding work on the stream; not in the
+                         the flattened extrema are sorted on the device, with
+                         every count kept there, so the call is as
+                         asynchronous as the block-scope one; not in the
                          batched form: TOPOSZP_E_UNSUPPORTED there) */
   int32_t rbf_policy; /* 0 = adaptive kernel size/width (default),
                          1 = always k_size 3 */

@@ -49,7 +49,6 @@
 #include <type_traits>
 #include <vector>
 
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "toposzp.h"
 
@@ -478,6 +477,7 @@ struct EncArgs {
   unsigned* vals;            // and their point indices
   unsigned long long* skeys; // each wave's staging slice of keys (indexed like points)
   unsigned* svals;           // and of indices
+  unsigned* ccnt;            // field scope: flattened extrema per chunk
   const int* delta;          // field scope: ranks per point for the encode pass
 };
 
@@ -1192,18 +1192,18 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     }
   }
   if (MODE == kModeMark) {
-    // one range of the compacted arrays per workgroup from the field-wide
-    // counter; each wave then copies its slice there (the barrier makes the
-    // slices visible to the whole workgroup).  Errors are the encode pass's.
+    // the chunk's keys, compacted at the start of its own region of the
+    // arrays (its first point's index): each wave copies its slice after the
+    // slices of the waves before it, and the chunk's count goes out for the
+    // scan.  Errors are the encode pass's.
     if (lane == 0) sh.pfd[wv] = wcnt;
     __syncthreads();
     if (tid == 0) {
       int tot = 0;
       for (int w = 0; w < WAVES; ++w) tot += sh.pfd[w];
-      sh.pfr[0] = tot ? (int)atomicAdd(&ctrl_of(a.ws)->fs_count, (unsigned)tot) : 0;
+      a.ccnt[c] = (unsigned)tot;
     }
-    __syncthreads();
-    int off = sh.pfr[0];
+    int off = c * kChunk;
     for (int w = 0; w < wv; ++w) off += sh.pfd[w];
     const size_t sb = (size_t)bw * kB;
     for (int j = lane; j < wcnt; j += 64) {
@@ -1283,15 +1283,118 @@ encode_kernel(EncArgs a) {
 }
 
 // Clears the field-scope mark counter ahead of the mark pass.
-__global__ void fs_clear_kernel(uint8_t* ws) {
-  if (threadIdx.x == 0) ctrl_of(ws)->fs_count = 0;
+// Field-scope ranks (Section IV-A (2) read field-wide): the flattened extrema
+// of the whole field are put in the order of their sort keys (class, bin,
+// then less extreme first) by a merge sort whose every size is read on the
+// device, so the call never waits for the host.  Each chunk's keys are sorted
+// in LDS into a run; runs of 2^L chunks are then merged pairwise, each key
+// finding its place in the merged run by one binary search in the other
+// run.
+
+// Exclusive scan of the chunks' counts (one workgroup of 1024 threads):
+// coff[c] = keys of the chunks before c, coff[nch] = all of them.
+__global__ __launch_bounds__(1024) void fs_scan_kernel(const unsigned* __restrict__ ccnt, unsigned* coff, int nch,
+                                                       uint8_t* ws) {
+  __shared__ unsigned s_w[16];
+  __shared__ unsigned s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nch; base += 1024) {
+    const int c = base + tid;
+    const unsigned v = c < nch ? ccnt[c] : 0u;
+    const unsigned incl = (unsigned)wave_incl_scan((int)v, lane);
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    unsigned wbase = s_carry;
+    for (int w = 0; w < wv; ++w) wbase += s_w[w];
+    if (c < nch) coff[c] = wbase + incl - v;
+    __syncthreads();
+    if (tid == 1023) s_carry = wbase + incl;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    coff[nch] = s_carry;
+    ctrl_of(ws)->fs_count = s_carry;
+  }
+}
+
+// One workgroup per chunk: its m keys (at most one per point) into LDS, each
+// placed by the count of keys before it (smaller, or equal with a smaller
+// index), and written as the chunk's sorted run at coff[c].
+constexpr int kFsThreads = 256;
+__global__ __launch_bounds__(kFsThreads) void fs_sort_kernel(const unsigned long long* __restrict__ keys,
+                                                             const unsigned* __restrict__ vals,
+                                                             const unsigned* __restrict__ ccnt,
+                                                             const unsigned* __restrict__ coff,
+                                                             unsigned long long* okeys, unsigned* ovals) {
+  __shared__ unsigned long long s_k[kChunk];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int m = (int)ccnt[c];
+  const size_t src = (size_t)c * kChunk;
+  for (int e = tid; e < m; e += kFsThreads) s_k[e] = keys[src + e];
+  __syncthreads();
+  const unsigned base = coff[c];
+  for (int e = tid; e < m; e += kFsThreads) {
+    const unsigned long long k = s_k[e];
+    int pos = 0;
+    for (int j = 0; j < m; ++j) {
+      const unsigned long long kj = s_k[j];
+      pos += (kj < k || (kj == k && j < e)) ? 1 : 0;
+    }
+    okeys[base + pos] = k;
+    ovals[base + pos] = vals[src + e];
+  }
+}
+
+// First index in [lo, hi) whose key is >= k (upper: > k).
+template <bool UPPER>
+__device__ __forceinline__ unsigned fs_bound(const unsigned long long* __restrict__ keys, unsigned lo, unsigned hi,
+                                             unsigned long long k) {
+  while (lo < hi) {
+    const unsigned mid = (lo + hi) >> 1;
+    const unsigned long long km = keys[mid];
+    if (UPPER ? km <= k : km < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Merge pass L: the runs of chunks [2j 2^L, (2j+1) 2^L) and
+// [(2j+1) 2^L, (2j+2) 2^L) become one run.  A key of the left run goes
+// after the right run's smaller keys, one of the right run after the left
+// run's smaller or equal keys, so equal keys keep their order.
+__global__ __launch_bounds__(256) void fs_merge_kernel(const unsigned long long* __restrict__ keys,
+                                                       const unsigned* __restrict__ vals,
+                                                       const unsigned* __restrict__ coff, int nch, int L,
+                                                       unsigned long long* okeys, unsigned* ovals) {
+  const unsigned total = coff[nch];
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < total; i += gridDim.x * 256u) {
+    // the chunk holding entry i: the last c with coff[c] <= i
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (coff[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b0 = (lo >> (L + 1)) << (L + 1);
+    const int bm = min(b0 + (1 << L), nch), be = min(b0 + (2 << L), nch);
+    const unsigned sL = coff[b0], sR = coff[bm], eR = coff[be];
+    const unsigned long long k = keys[i];
+    const unsigned pos = i < sR ? (i - sL) + (fs_bound<false>(keys, sR, eR, k) - sR)
+                                : (i - sR) + (fs_bound<true>(keys, sL, sR, k) - sL);
+    okeys[sL + pos] = k;
+    ovals[sL + pos] = vals[i];
+  }
 }
 
 // Field-scope ranks from the sorted keys: a flattened extremum's rank is 1 +
 // the number of entries of its (class, bin) group sorted before its value
 // (ties share a rank).  Both starts are lower bounds in the sorted prefix.
 __global__ __launch_bounds__(256) void fs_rank_kernel(const unsigned long long* __restrict__ keys,
-                                                      const unsigned* __restrict__ vals, int n, int* delta) {
+                                                      const unsigned* __restrict__ vals,
+                                                      const unsigned* __restrict__ coff, int nch, int* delta) {
+  const int n = (int)coff[nch];
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const unsigned long long k = keys[i];
     const unsigned long long gk = k & ~0xFFFFFFFFull;
@@ -3412,25 +3515,22 @@ void ev_end(int k, hipStream_t s) {
 }
 
 // Field-scope compression: sort keys and indices (in and out), ranks per
-// point and the sort's temporary storage, after the compression region.
+// point, and the per-chunk counts and their scan, after the compression
+// region.
 struct FieldLayout {
-  uint64_t keys_in, vals_in, keys_out, vals_out, delta, tmp, end;
-  size_t tmp_bytes;
+  uint64_t keys_in, vals_in, keys_out, vals_out, delta, ccnt, coff, end;
 };
 FieldLayout field_layout(const HostGeom& hg) {
   FieldLayout F;
   const uint64_t n = (uint64_t)hg.g.n;
-  F.tmp_bytes = 0;
-  (void)rocprim::radix_sort_pairs(nullptr, F.tmp_bytes, (const unsigned long long*)nullptr,
-                                  (unsigned long long*)nullptr, (const unsigned*)nullptr, (unsigned*)nullptr,
-                                  (unsigned)n, 0, 56, (hipStream_t)0);
   F.keys_in = al256(comp_layout(hg.nch, 1).end);
   F.vals_in = al256(F.keys_in + 8 * n);
   F.keys_out = al256(F.vals_in + 4 * n);
   F.vals_out = al256(F.keys_out + 8 * n);
   F.delta = al256(F.vals_out + 4 * n);
-  F.tmp = al256(F.delta + 4 * n);
-  F.end = al256(F.tmp + F.tmp_bytes);
+  F.ccnt = al256(F.delta + 4 * n);
+  F.coff = al256(F.ccnt + 4 * hg.nch);
+  F.end = al256(F.coff + 4 * (hg.nch + 1));
   return F;
 }
 size_t ws_need_field(const HostGeom& hg) {
@@ -3539,6 +3639,7 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
   ea.vals = nullptr;
   ea.skeys = nullptr;
   ea.svals = nullptr;
+  ea.ccnt = nullptr;
   ea.delta = nullptr;
   if (field) {
     // the mark pass stages in the sort's output arrays, compacts into its input
@@ -3547,6 +3648,7 @@ int build_comp(const float* d_field, uint32_t ndim, const uint64_t* dims, int eb
     ea.vals = reinterpret_cast<unsigned*>(d_ws + F.vals_in);
     ea.skeys = reinterpret_cast<unsigned long long*>(d_ws + F.keys_out);
     ea.svals = reinterpret_cast<unsigned*>(d_ws + F.vals_out);
+    ea.ccnt = reinterpret_cast<unsigned*>(d_ws + F.ccnt);
     ea.delta = reinterpret_cast<const int*>(d_ws + F.delta);
   }
 
@@ -3793,39 +3895,38 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
   ev_begin(1, s);
   if (ea.field) {
     // field-scope ranks: the mark pass compacts the flattened extrema's sort
-    // keys; their count comes back to the host (the one synchronisation of
-    // this path), the keys are sorted by (class, bin, order) and ranked, and
-    // the encode pass reads the ranks
+    // keys per chunk; their counts are scanned, the keys sorted by (class,
+    // bin, order) and ranked, and the encode pass reads the ranks.  Every
+    // count stays on the device.
     HostGeom hg;
     (void)host_geom(ndim, dims, &hg);
     const FieldLayout F = field_layout(hg);
     uint8_t* ws = (uint8_t*)d_ws;
     const unsigned grid = xcd_grid(ea.nch);
-    hipLaunchKernelGGL(fs_clear_kernel, dim3(1), dim3(64), 0, s, ws);
     if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
     else hipLaunchKernelGGL((encode_kernel<2, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
-    unsigned cnt = 0;
-    if (hipMemcpyAsync(&cnt, ws + offsetof(Ctrl, fs_count), sizeof cnt, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return TOPOSZP_E_DEVICE;
-    if ((uint64_t)cnt > (uint64_t)ea.gd.n) return TOPOSZP_E_DEVICE;
-    if (cnt) {
-      size_t tb = 0;
-      if (rocprim::radix_sort_pairs(nullptr, tb, (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
-                                    (const unsigned*)nullptr, (unsigned*)nullptr, cnt, 0, 56, s) != hipSuccess)
-        return TOPOSZP_E_DEVICE;
-      if (tb > F.tmp_bytes) return TOPOSZP_E_CAPACITY;
-      if (rocprim::radix_sort_pairs(ws + F.tmp, tb, reinterpret_cast<const unsigned long long*>(ws + F.keys_in),
-                                    reinterpret_cast<unsigned long long*>(ws + F.keys_out),
-                                    reinterpret_cast<const unsigned*>(ws + F.vals_in),
-                                    reinterpret_cast<unsigned*>(ws + F.vals_out), cnt, 0, 56, s) != hipSuccess)
-        return TOPOSZP_E_DEVICE;
-      const unsigned rg = (unsigned)std::min<long long>(((long long)cnt + 255) / 256, 4096);
-      hipLaunchKernelGGL(fs_rank_kernel, dim3(rg), dim3(256), 0, s,
-                         reinterpret_cast<const unsigned long long*>(ws + F.keys_out),
-                         reinterpret_cast<const unsigned*>(ws + F.vals_out), (int)cnt,
-                         reinterpret_cast<int*>(ws + F.delta));
+    auto K = [&](uint64_t o) { return reinterpret_cast<unsigned long long*>(ws + o); };
+    auto V = [&](uint64_t o) { return reinterpret_cast<unsigned*>(ws + o); };
+    const unsigned* ccnt = V(F.ccnt);
+    const unsigned* coff = V(F.coff);
+    hipLaunchKernelGGL(fs_scan_kernel, dim3(1), dim3(1024), 0, s, ccnt, V(F.coff), ea.nch, ws);
+    // runs of one chunk into the "out" arrays, then pairwise merges back and
+    // forth; the sorted keys end where the last pass wrote them
+    hipLaunchKernelGGL(fs_sort_kernel, dim3(ea.nch), dim3(kFsThreads), 0, s, K(F.keys_in), V(F.vals_in), ccnt,
+                       coff, K(F.keys_out), V(F.vals_out));
+    const unsigned mg = (unsigned)std::min<uint64_t>(((uint64_t)hg.g.n + 1023) / 1024, 2048);
+    bool in_out = true;  // the current run arrays are the "out" ones
+    for (int L = 0; (1 << L) < ea.nch; ++L) {
+      if (in_out)
+        hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, K(F.keys_out), V(F.vals_out), coff,
+                           ea.nch, L, K(F.keys_in), V(F.vals_in));
+      else
+        hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, K(F.keys_in), V(F.vals_in), coff,
+                           ea.nch, L, K(F.keys_out), V(F.vals_out));
+      in_out = !in_out;
     }
+    hipLaunchKernelGGL(fs_rank_kernel, dim3(mg), dim3(256), 0, s, K(in_out ? F.keys_out : F.keys_in),
+                       V(in_out ? F.vals_out : F.vals_in), coff, ea.nch, reinterpret_cast<int*>(ws + F.delta));
     if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
     else hipLaunchKernelGGL((encode_kernel<2, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
   } else {

@@ -134,6 +134,12 @@ class Server:
         self._bid += 1
         comp = [r for r in reqs if r.op == "compress"]
         dec = [r for r in reqs if r.op == "decompress"]
+        # the batch's inputs may still be in production on the submitting
+        # stream: order the batch after it, and tell the allocator that the
+        # inputs are in use on this stream until the batch ends
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        for r in reqs:
+            r.src.record_stream(s)
         with torch.cuda.stream(s):
             if comp:
                 b.comp = tsz.CompressBatch([r.src for r in comp], [r.eb for r in comp], [r.mode for r in comp],
@@ -155,16 +161,25 @@ class Server:
         return True
 
     def _complete(self, b: _Batch, t: float):
+        import torch
         comp = [r for r in b.reqs if r.op == "compress"]
         dec = [r for r in b.reqs if r.op == "decompress"]
+        # results were made on the batch's stream; the caller uses them on
+        # its own, so the allocator must not reuse them for the batch stream
+        # while work the caller enqueues there may still read them
+        consumer = torch.cuda.current_stream(self.device)
         if b.comp is not None:
             st, streams = b.comp.results()
             for r, s_, out in zip(comp, st, streams):
                 r.status, r.result = int(s_), out
+                if self.keep_results:
+                    out.record_stream(consumer)
         if b.dec is not None:
             st = b.dec.status.cpu().tolist()
             for r, s_, rec in zip(dec, st, b.dec.recs):
                 r.status, r.result = int(s_), rec
+                if self.keep_results:
+                    rec.record_stream(consumer)
         for r in b.reqs:
             r.done = t
             if not self.keep_results:
