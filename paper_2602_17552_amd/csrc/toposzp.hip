@@ -780,6 +780,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   constexpr int BPW = kB / WAVES;  // blocks per wave
   constexpr int MAXWR = MODE == kModeField ? kMaxWRankAny : kMaxWRankBlk;
   static_assert(BPW % 4 == 0, "four blocks in flight per wave");
+  static_assert(BPW <= 32, "per-wave block masks are 32-bit");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const GeomD& g = a.gd;
@@ -806,7 +807,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   // consecutive rows of one plane (nx >= 64).  xbm marks interior blocks
   // with a point at x = 0 or x = nx - 1; l0, l1 are the lanes of those
   // points in block k.
-  unsigned long long fastm = 0, xbm = 0;
+  unsigned fastm = 0, xbm = 0;  // bits [0, BPW): at most 16 blocks per wave
   int l0v = 0, l1v = 0;
   if (fast_mode) {
     const int b = bw + (lane < BPW ? lane : 0);
@@ -821,8 +822,8 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     const int xe = x + kB - 1;
     ok = ok && y >= 1 && y + (xe >= g.nx ? 1 : 0) <= g.ny - 2;
     const bool xb = x == 0 || xe >= g.nx - 1;
-    fastm = __ballot(ok && !xb);
-    xbm = __ballot(ok && xb);
+    fastm = (unsigned)__ballot(ok && !xb);  // lanes >= BPW never set ok
+    xbm = (unsigned)__ballot(ok && xb);
     l0v = x == 0 ? 0 : g.nx - x;
     l1v = g.nx - 1 - x;
   }
@@ -843,7 +844,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
   };
   const int n = g.n;
   const unsigned ndeg = (g.nx > 1 ? 1u : 0u) | (g.ny > 1 ? 4u : 0u) | (ND == 3 && g.nz > 1 ? 16u : 0u);
-  unsigned long long nfm = 0, qom = 0;  // lanes with a non-finite value, |q| too large
+  bool nfm = false, qom = false;  // some lane had a non-finite value, |q| too large
   bool wover = false;
 
   const unsigned lab_shift = 2u * (unsigned)(lane & 15);
@@ -875,9 +876,9 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     // decided with one compare per lane and scalar mask algebra
     const unsigned long long vm = n - b0 >= kB ? ~0ull : ((1ull << (n - b0)) - 1ull);
     const float av = in.c;
-    nfm |= __ballot(!isfinite(av)) & vm;
+    nfm |= (__ballot(!isfinite(av)) & vm) != 0;
     int q = quantize(av, inv2e, ed);
-    qom |= __ballot((unsigned)(q + kQMax) > 2u * kQMax) & vm;
+    qom |= (__ballot((unsigned)(q + kQMax) > 2u * kQMax) & vm) != 0;
     unsigned long long m_min = 0, m_max = 0, m_sad = 0, lostm = 0;
     if (topo) {
       const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(in.xe)));
@@ -1119,8 +1120,12 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     const unsigned od = o & 0xFFFFFFu, orr = o >> 24;
     const int w = od ? 32 - __builtin_clz(od) : 0;
     const int wr = orr ? 32 - __builtin_clz(orr) : 0;
-    put_planes<kMaxWData>(md, w, stg_d + (size_t)b * 2 * kMaxWData, lane);
-    put_planes<kMaxWRankBlk>(mr, wr, stg_r + (size_t)b * 2 * kMaxWRankBlk, lane);
+    // 2-bit labels (Section IV-A (1)), 16 points per dword: bit 0 marks an
+    // extremum, bit 1 a saddle or maximum (m=01, s=10, M=11).  The labels
+    // and the block's fixed-size parts go out before the planes, so that no
+    // classification mask stays live across the plane runs.
+    const unsigned lv = row_or_last((lane_in(m_min | m_max) ? lab_b0 : 0u) | (lane_in(m_sad | m_max) ? lab_b1 : 0u));
+    if ((lane & 15) == 15) lab_w[4 * k] = lv;
     // lane 0 holds the block's first value and first rank
     if (lane == 0) {
       wd_w[k] = w;
@@ -1130,10 +1135,8 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       rsign_w[k] = rsign;
       rfirst_w[k] = delta;
     }
-    // 2-bit labels (Section IV-A (1)), 16 points per dword: bit 0 marks an
-    // extremum, bit 1 a saddle or maximum (m=01, s=10, M=11)
-    const unsigned lv = row_or_last((lane_in(m_min | m_max) ? lab_b0 : 0u) | (lane_in(m_sad | m_max) ? lab_b1 : 0u));
-    if ((lane & 15) == 15) lab_w[4 * k] = lv;
+    put_planes<kMaxWData>(md, w, stg_d + (size_t)b * 2 * kMaxWData, lane);
+    put_planes<kMaxWRankBlk>(mr, wr, stg_r + (size_t)b * 2 * kMaxWRankBlk, lane);
     return true;
   };
 
@@ -1153,7 +1156,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       unroll<0, BPW>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const EncIn& in = P[k % kDepth];
-        if ((fastm >> k) & 1ull) {
+        if ((fastm >> k) & 1u) {
           if (block_fast(in, kc, std::false_type{}, ~0ull, ~0ull)) todo &= ~(1u << k);
         }
         if constexpr (k + kDepth < BPW) P[k % kDepth] = fetch(k + kDepth);
@@ -1167,7 +1170,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       const int k = __ffs((int)todo) - 1;
       todo &= todo - 1;
       const EncIn in = enc_fetch<ND>(f, bw + k, lane, g);
-      if ((xbm >> k) & 1ull) {
+      if ((xbm >> k) & 1u) {
         const int l0 = __builtin_amdgcn_readlane(l0v, k), l1 = __builtin_amdgcn_readlane(l1v, k);
         const unsigned long long xm0 = l0 < kB ? ~(1ull << l0) : ~0ull, xm1 = l1 < kB ? ~(1ull << l1) : ~0ull;
         if (block_fast(in, k, std::true_type{}, xm0, xm1)) continue;
@@ -1213,7 +1216,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     return;
   }
   {
-    const bool nf = nfm != 0, qo = qom != 0 || wover;
+    const bool nf = nfm, qo = qom || wover;
     if (lane == 0) sh.wfl[wv] = wflag | (nf ? 1u : 0u) | (qo ? 4u : 0u);
   }
   // this wave's blocks' fixed-size parts, from its own LDS slots (written
