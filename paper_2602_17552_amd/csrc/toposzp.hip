@@ -794,7 +794,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
 
   // interior blocks of a topology stream in block scope take block_fast
   // (below) when the field is at least 64 wide
-  const bool fast_mode = MODE == kModeBlock && topo && g.nx >= kB;
+  const bool fast_mode = topo && g.nx >= kB;
   // a wave whose blocks read only inside the field loads without clamping
   const bool inner = fast_mode && reads_inside<ND>(bw, g) && reads_inside<ND>(bw + BPW - 1, g);
   const unsigned xoff = lane == 0 ? 0u : 65u;
@@ -1013,8 +1013,9 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     }
   };
 
-  // An interior block (see fast_mode below) in block scope: the same parts
-  // as `block` with fewer instructions.  The bin index comes from a float
+  // An interior block (see fast_mode below), in any mode: the same parts
+  // (or, in the mark pass, the same sort keys) as `block` with fewer
+  // instructions.  The bin index comes from a float
   // estimate t whose exact float edges lo = (2t-1)e and hi = (2t+1)e,
   // rounded up, decide both the point's own bin (t is its bin iff
   // lo <= a < hi) and its neighbours' (a neighbour shares the bin iff it
@@ -1077,12 +1078,30 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       m_sad = (bgx & bly) | (blx & bgy);
     }
     const unsigned long long lostm = (m_min | m_max | m_sad) & same;
-    // ranks (Section IV-A (2)), as in `block`; with at most one flattened
-    // extremum per (class, bin) every rank is 1, which is the common case,
-    // so the pairwise count runs only when two of them share a bin and class
     const unsigned long long ext = lostm & (m_min | m_max);
+    if constexpr (MODE == kModeMark) {
+      // the sort keys of the flattened extrema, as in `block`
+      if (ext) {
+        const bool ismax = lane_in(m_max);
+        const unsigned ord = (unsigned)(ismax ? fkey(av) : -fkey(av)) ^ 0x80000000u;
+        const unsigned long long key = ((unsigned long long)(ismax ? 1u : 0u) << 55) |
+                                       ((unsigned long long)(unsigned)(q + (1 << 22)) << 32) | ord;
+        if (lane_in(ext)) {
+          const int pos = wcnt + (int)mbcnt(ext);
+          a.skeys[(size_t)bw * kB + pos] = key;
+          a.svals[(size_t)bw * kB + pos] = (unsigned)(b * kB + lane);
+        }
+        wcnt += __popcll(ext);
+      }
+      return true;
+    }
+    // ranks (Section IV-A (2)): in field scope from the sorted pass (a
+    // flattened saddle gets 1); in block scope as in `block`, where with at
+    // most one flattened extremum per (class, bin) every rank is 1, the
+    // common case, so the pairwise count runs only when two of them share a
+    // bin and class
     int cnt = 0;
-    if (ext & (ext - 1)) {
+    if (MODE == kModeBlock && (ext & (ext - 1))) {
       const int ck = (q << 1) | (lane_in(m_max) ? 1 : 0);
       unsigned shared = 0;
       unsigned long long m = ext;
@@ -1103,7 +1122,8 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
         }
       }
     }
-    const int delta = (lane_in(lostm) ? 1 : 0) + (lane_in(ext) ? cnt : 0);
+    const int delta = MODE == kModeField ? (lane_in(ext) ? a.delta[b * kB + lane] : (lane_in(lostm) ? 1 : 0))
+                                         : (lane_in(lostm) ? 1 : 0) + (lane_in(ext) ? cnt : 0);
     // B + LZ (residual i = v_i - v_{i-1}, residual 0 = 0) and BE of the bin
     // indices (offset by 2^31 so that unsigned order is signed order) and of
     // the ranks; one OR over the wave gives both widths (data below bit 24,
@@ -1116,8 +1136,10 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     const unsigned pr = (unsigned)dpp_from_prev((int)ud, (int)ud);
     const unsigned mr = absdiff_u32(ud, pr);
     const unsigned long long rsign = __ballot(ud < pr);
-    const unsigned o = wave_or(md | (mr << 24));
-    const unsigned od = o & 0xFFFFFFu, orr = o >> 24;
+    // (field-scope ranks may take all 31 bits: two ORs there)
+    const unsigned o = MODE == kModeField ? 0u : wave_or(md | (mr << 24));
+    const unsigned od = MODE == kModeField ? wave_or(md) : o & 0xFFFFFFu;
+    const unsigned orr = MODE == kModeField ? wave_or(mr) : o >> 24;
     const int w = od ? 32 - __builtin_clz(od) : 0;
     const int wr = orr ? 32 - __builtin_clz(orr) : 0;
     // 2-bit labels (Section IV-A (1)), 16 points per dword: bit 0 marks an
@@ -1136,7 +1158,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
       rfirst_w[k] = delta;
     }
     put_planes<kMaxWData>(md, w, stg_d + (size_t)b * 2 * kMaxWData, lane);
-    put_planes<kMaxWRankBlk>(mr, wr, stg_r + (size_t)b * 2 * kMaxWRankBlk, lane);
+    put_planes<MAXWR>(mr, wr, stg_r + (size_t)b * 2 * MAXWR, lane);
     return true;
   };
 
@@ -1350,7 +1372,7 @@ __global__ __launch_bounds__(kFsThreads) void fs_sort_kernel(const unsigned long
   }
 }
 
-// First index in [lo, hi) whose key is >= k (upper: > k).
+// First index in [lo, hi) whose key is >= k (UPPER: > k).
 template <bool UPPER>
 __device__ __forceinline__ unsigned fs_bound(const unsigned long long* __restrict__ keys, unsigned lo, unsigned hi,
                                              unsigned long long k) {
@@ -1363,31 +1385,34 @@ __device__ __forceinline__ unsigned fs_bound(const unsigned long long* __restric
   return lo;
 }
 
-// Merge pass L: the runs of chunks [2j 2^L, (2j+1) 2^L) and
-// [(2j+1) 2^L, (2j+2) 2^L) become one run.  A key of the left run goes
-// after the right run's smaller keys, one of the right run after the left
-// run's smaller or equal keys, so equal keys keep their order.
+// Merge pass L: the four runs of chunks [b0 + r 4^L, b0 + (r+1) 4^L),
+// r = 0..3, b0 a multiple of 4^(L+1), become one run.  A key of run r goes
+// after the smaller or equal keys of the runs before it and the smaller keys
+// of the runs after it, so equal keys keep their order; its three searches
+// are independent.  A key's run follows from the chunk it came from, its
+// point index / kChunk: merging only moves keys within their run.
 __global__ __launch_bounds__(256) void fs_merge_kernel(const unsigned long long* __restrict__ keys,
                                                        const unsigned* __restrict__ vals,
                                                        const unsigned* __restrict__ coff, int nch, int L,
                                                        unsigned long long* okeys, unsigned* ovals) {
   const unsigned total = coff[nch];
   for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < total; i += gridDim.x * 256u) {
-    // the chunk holding entry i: the last c with coff[c] <= i
-    int lo = 0, hi = nch - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (coff[mid] <= i) lo = mid;
-      else hi = mid - 1;
-    }
-    const int b0 = (lo >> (L + 1)) << (L + 1);
-    const int bm = min(b0 + (1 << L), nch), be = min(b0 + (2 << L), nch);
-    const unsigned sL = coff[b0], sR = coff[bm], eR = coff[be];
+    const unsigned v = vals[i];
+    const int c = (int)(v / (unsigned)kChunk);
+    const int b0 = (c >> (2 * L + 2)) << (2 * L + 2);
+    unsigned S[5];
+#pragma unroll
+    for (int r = 0; r <= 4; ++r) S[r] = coff[min(b0 + (r << (2 * L)), nch)];
+    const int own = (c - b0) >> (2 * L);  // 0..3
     const unsigned long long k = keys[i];
-    const unsigned pos = i < sR ? (i - sL) + (fs_bound<false>(keys, sR, eR, k) - sR)
-                                : (i - sR) + (fs_bound<true>(keys, sL, sR, k) - sL);
-    okeys[sL + pos] = k;
-    ovals[sL + pos] = vals[i];
+    unsigned pos = i - S[own];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < own) pos += fs_bound<true>(keys, S[r], S[r + 1], k) - S[r];
+      else if (r > own) pos += fs_bound<false>(keys, S[r], S[r + 1], k) - S[r];
+    }
+    okeys[S[0] + pos] = k;
+    ovals[S[0] + pos] = v;
   }
 }
 
@@ -1397,24 +1422,13 @@ __global__ __launch_bounds__(256) void fs_merge_kernel(const unsigned long long*
 __global__ __launch_bounds__(256) void fs_rank_kernel(const unsigned long long* __restrict__ keys,
                                                       const unsigned* __restrict__ vals,
                                                       const unsigned* __restrict__ coff, int nch, int* delta) {
-  const int n = (int)coff[nch];
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+  const unsigned n = coff[nch];
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
     const unsigned long long k = keys[i];
     const unsigned long long gk = k & ~0xFFFFFFFFull;
-    int lo = 0, hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (keys[mid] < gk) lo = mid + 1;
-      else hi = mid;
-    }
-    const int g0 = lo;
-    hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (keys[mid] < k) lo = mid + 1;
-      else hi = mid;
-    }
-    delta[vals[i]] = 1 + lo - g0;
+    const unsigned g0 = fs_bound<false>(keys, 0, i, gk);
+    const unsigned t0 = fs_bound<false>(keys, g0, i, k);
+    delta[vals[i]] = (int)(1 + t0 - g0);
   }
 }
 
@@ -3913,13 +3927,13 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     const unsigned* ccnt = V(F.ccnt);
     const unsigned* coff = V(F.coff);
     hipLaunchKernelGGL(fs_scan_kernel, dim3(1), dim3(1024), 0, s, ccnt, V(F.coff), ea.nch, ws);
-    // runs of one chunk into the "out" arrays, then pairwise merges back and
+    // runs of one chunk into the "out" arrays, then four-way merges back and
     // forth; the sorted keys end where the last pass wrote them
     hipLaunchKernelGGL(fs_sort_kernel, dim3(ea.nch), dim3(kFsThreads), 0, s, K(F.keys_in), V(F.vals_in), ccnt,
                        coff, K(F.keys_out), V(F.vals_out));
     const unsigned mg = (unsigned)std::min<uint64_t>(((uint64_t)hg.g.n + 1023) / 1024, 2048);
     bool in_out = true;  // the current run arrays are the "out" ones
-    for (int L = 0; (1 << L) < ea.nch; ++L) {
+    for (int L = 0; (1ll << (2 * L)) < ea.nch; ++L) {
       if (in_out)
         hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, K(F.keys_out), V(F.vals_out), coff,
                            ea.nch, L, K(F.keys_in), V(F.vals_in));
