@@ -3920,8 +3920,8 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     const FieldLayout F = field_layout(hg);
     uint8_t* ws = (uint8_t*)d_ws;
     const unsigned grid = xcd_grid(ea.nch);
-    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
-    else hipLaunchKernelGGL((encode_kernel<2, 4, kModeMark>), dim3(grid), dim3(256), 0, s, ea);
+    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 8, kModeMark>), dim3(grid), dim3(512), 0, s, ea);
+    else hipLaunchKernelGGL((encode_kernel<2, 8, kModeMark>), dim3(grid), dim3(512), 0, s, ea);
     auto K = [&](uint64_t o) { return reinterpret_cast<unsigned long long*>(ws + o); };
     auto V = [&](uint64_t o) { return reinterpret_cast<unsigned*>(ws + o); };
     const unsigned* ccnt = V(F.ccnt);
@@ -3944,8 +3944,8 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     }
     hipLaunchKernelGGL(fs_rank_kernel, dim3(mg), dim3(256), 0, s, K(in_out ? F.keys_out : F.keys_in),
                        V(in_out ? F.vals_out : F.vals_in), coff, ea.nch, reinterpret_cast<int*>(ws + F.delta));
-    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
-    else hipLaunchKernelGGL((encode_kernel<2, 4, kModeField>), dim3(grid), dim3(256), 0, s, ea);
+    if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 8, kModeField>), dim3(grid), dim3(512), 0, s, ea);
+    else hipLaunchKernelGGL((encode_kernel<2, 8, kModeField>), dim3(grid), dim3(512), 0, s, ea);
   } else {
     launch_encode((int)ndim, tune_now().encode_waves, xcd_grid(ea.nch), s, ea);
   }
