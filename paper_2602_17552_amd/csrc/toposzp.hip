@@ -1416,6 +1416,57 @@ __global__ __launch_bounds__(256) void fs_merge_kernel(const unsigned long long*
   }
 }
 
+// Merge pass L as fs_merge_kernel, with one workgroup per group of four
+// runs and the group's keys staged in LDS, so the searches read LDS.  For
+// the low levels, where groups are many and small; a group larger than the
+// staging area searches its keys in global memory.
+constexpr int kFsMergeCap = 8192;
+__global__ __launch_bounds__(1024) void fs_merge_lds_kernel(const unsigned long long* __restrict__ keys,
+                                                            const unsigned* __restrict__ vals,
+                                                            const unsigned* __restrict__ coff, int nch, int L,
+                                                            unsigned long long* okeys, unsigned* ovals) {
+  __shared__ unsigned long long s_k[kFsMergeCap];
+  const long long b0l = (long long)blockIdx.x << (2 * L + 2);
+  if (b0l >= nch) return;
+  const int b0 = (int)b0l;
+  unsigned S[5];
+#pragma unroll
+  for (int r = 0; r <= 4; ++r) S[r] = coff[(int)min((long long)b0 + ((long long)r << (2 * L)), (long long)nch)];
+  const unsigned m = S[4] - S[0];
+  unsigned R[5];
+#pragma unroll
+  for (int r = 0; r <= 4; ++r) R[r] = S[r] - S[0];
+  const unsigned long long* gk = keys + S[0];
+  // the position of key e (run own) in the merged group, searching in `src`
+  auto place = [&](const unsigned long long* src, unsigned e, unsigned long long k) {
+    const int own = (e >= R[1] ? 1 : 0) + (e >= R[2] ? 1 : 0) + (e >= R[3] ? 1 : 0);
+    unsigned pos = e - R[own];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < own) pos += fs_bound<true>(src, R[r], R[r + 1], k) - R[r];
+      else if (r > own) pos += fs_bound<false>(src, R[r], R[r + 1], k) - R[r];
+    }
+    return pos;
+  };
+  if (m <= (unsigned)kFsMergeCap) {
+    for (unsigned e = threadIdx.x; e < m; e += blockDim.x) s_k[e] = gk[e];
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < m; e += blockDim.x) {
+      const unsigned long long k = s_k[e];
+      const unsigned pos = place(s_k, e, k);
+      okeys[S[0] + pos] = k;
+      ovals[S[0] + pos] = vals[S[0] + e];
+    }
+  } else {
+    for (unsigned e = threadIdx.x; e < m; e += blockDim.x) {
+      const unsigned long long k = gk[e];
+      const unsigned pos = place(gk, e, k);
+      okeys[S[0] + pos] = k;
+      ovals[S[0] + pos] = vals[S[0] + e];
+    }
+  }
+}
+
 // Field-scope ranks from the sorted keys: a flattened extremum's rank is 1 +
 // the number of entries of its (class, bin) group sorted before its value
 // (ties share a rank).  Both starts are lower bounds in the sorted prefix.
@@ -3934,12 +3985,18 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     const unsigned mg = (unsigned)std::min<uint64_t>(((uint64_t)hg.g.n + 1023) / 1024, 2048);
     bool in_out = true;  // the current run arrays are the "out" ones
     for (int L = 0; (1ll << (2 * L)) < ea.nch; ++L) {
-      if (in_out)
-        hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, K(F.keys_out), V(F.vals_out), coff,
-                           ea.nch, L, K(F.keys_in), V(F.vals_in));
+      // one LDS workgroup per group while the groups are many, then the
+      // grid-wide pass with its searches in L2
+      const long long groups = ((long long)ea.nch + (1ll << (2 * L + 2)) - 1) >> (2 * L + 2);
+      const unsigned long long* ik = K(in_out ? F.keys_out : F.keys_in);
+      const unsigned* iv = V(in_out ? F.vals_out : F.vals_in);
+      unsigned long long* ok = K(in_out ? F.keys_in : F.keys_out);
+      unsigned* ov = V(in_out ? F.vals_in : F.vals_out);
+      if (groups >= 64)
+        hipLaunchKernelGGL(fs_merge_lds_kernel, dim3((unsigned)groups), dim3(1024), 0, s, ik, iv, coff, ea.nch, L, ok,
+                           ov);
       else
-        hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, K(F.keys_in), V(F.vals_in), coff,
-                           ea.nch, L, K(F.keys_out), V(F.vals_out));
+        hipLaunchKernelGGL(fs_merge_kernel, dim3(mg), dim3(256), 0, s, ik, iv, coff, ea.nch, L, ok, ov);
       in_out = !in_out;
     }
     hipLaunchKernelGGL(fs_rank_kernel, dim3(mg), dim3(256), 0, s, K(in_out ? F.keys_out : F.keys_in),
