@@ -65,6 +65,7 @@ def roofline_of(kernel, alg_bytes, ms, n, tag="1800x3600_rel1e-3"):
     out = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
            "traffic": cnt["bytes_per_launch"] if cnt else None, "alg_bytes": alg_bytes,
+           "traffic_over_alg": round(cnt["bytes_per_launch"] / alg_bytes, 3) if cnt else None,
            "ms": round(ms, 5)}
     if cnt and cnt.get("valu_per_launch"):
         ops = cnt["valu_per_launch"] * 64
@@ -342,6 +343,8 @@ def main():
                     help="length of the served-form trace at 200 req/s (0 skips it and the rate sweep)")
     ap.add_argument("--probe-workload", choices=["1800x3600", "256x256x256"], default="1800x3600",
                     help="with --probe: the field the probe steps run on")
+    ap.add_argument("--probe-topo", type=int, choices=[0, 1], default=1,
+                    help="with --probe: 0 compresses plain SZp streams (no topology parts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -371,8 +374,10 @@ def main():
     ws = tsz.Workspace(shape, dev)
     stream = torch.cuda.current_stream()
 
+    topo_kw = {"topo": False} if (args.probe and args.probe_topo == 0) else {}
+
     def comp(k):
-        tsz.compress_async(ins[k], EB, "rel", ws=ws, out=outs[k], size=sizes[k], status=cst)
+        tsz.compress_async(ins[k], EB, "rel", ws=ws, out=outs[k], size=sizes[k], status=cst, **topo_kw)
 
     # every copy compressed once so each has a stream of known size
     for k in range(R):

@@ -794,7 +794,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
 
   // interior blocks of a topology stream in block scope take block_fast
   // (below) when the field is at least 64 wide
-  const bool fast_mode = topo && g.nx >= kB;
+  const bool fast_mode = g.nx >= kB;
   // a wave whose blocks read only inside the field loads without clamping
   const bool inner = fast_mode && reads_inside<ND>(bw, g) && reads_inside<ND>(bw + BPW - 1, g);
   const unsigned xoff = lane == 0 ? 0u : 65u;
@@ -822,8 +822,9 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     const int xe = x + kB - 1;
     ok = ok && y >= 1 && y + (xe >= g.nx ? 1 : 0) <= g.ny - 2;
     const bool xb = x == 0 || xe >= g.nx - 1;
-    fastm = (unsigned)__ballot(ok && !xb);  // lanes >= BPW never set ok
-    xbm = (unsigned)__ballot(ok && xb);
+    // (plain SZp has no x neighbours to mask: its boundary blocks are fast too)
+    fastm = (unsigned)__ballot(ok && (!xb || !topo));  // lanes >= BPW never set ok
+    xbm = (unsigned)__ballot(ok && xb && topo);
     l0v = x == 0 ? 0 : g.nx - x;
     l1v = g.nx - 1 - x;
   }
@@ -1033,6 +1034,23 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     mul_round_up2(fmaf(t, 2.0f, -1.0f), fmaf(t, 2.0f, 1.0f), e, lo, hi);
     if (~(__ballot(av >= lo) & __ballot(av < hi) & __ballot(fabsf(t) <= (float)kQMax)) != 0ull) return false;
     const int q = (int)t;
+    if (!topo) {
+      // plain SZp: the bin indices' residuals, width and planes only
+      const unsigned qb = (unsigned)q ^ 0x80000000u;
+      const unsigned pb = (unsigned)dpp_from_prev((int)qb, (int)qb);
+      const unsigned md = absdiff_u32(qb, pb);
+      const unsigned long long sign = __ballot(qb < pb);
+      const unsigned od = wave_or(md);
+      const int w = od ? 32 - __builtin_clz(od) : 0;
+      if (lane == 0) {
+        wd_w[k] = w;
+        sign_w[k] = sign;
+        first_w[k] = q;
+        wr_w[k] = 0;
+      }
+      put_planes<kMaxWData>(md, w, stg_d + (size_t)b * 2 * kMaxWData, lane);
+      return true;
+    }
     // classification (Section III-A): strict compares with the face
     // neighbours; the x neighbours come from the adjacent lanes
     const float xl = __int_as_float(dpp_from_prev(__float_as_int(av), __float_as_int(in.xe)));

@@ -201,6 +201,12 @@ def test_parity_field_scope(tsz, ora, name, gen, eb, mode):
 def test_parity_plain_szp(tsz, ora):
     check(tsz, ora, "plain", datagen.gaussian_bumps_2d(90, 110, 5, seed=9), 1e-3, "rel", topo=False)
     check(tsz, ora, "plain3d", datagen.grf_3d(10, 12, 14, seed=9), 1e-3, "rel", topo=False)
+    # rows of at least 64 points: interior blocks, x-boundary ones included,
+    # take the fast path (several chunks and a partial last one)
+    check(tsz, ora, "plain_waves", datagen.sinusoids_2d(210, 333, 16, seed=10, noise_sd=1e-2), 1e-3, "rel",
+          topo=False)
+    check(tsz, ora, "plain_noise_abs", datagen.noise((130, 257), seed=11), 1e-2, "abs", topo=False)
+    check(tsz, ora, "plain3d_wide", datagen.grf_3d(12, 30, 70, seed=12), 1e-4, "rel", topo=False)
 
 
 def test_parity_adversarial_values(tsz, ora):
