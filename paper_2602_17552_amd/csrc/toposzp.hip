@@ -770,8 +770,10 @@ using EncShared = EncSharedT<kMaxWRankBlk>;
 using EncSharedField = EncSharedT<kMaxWRankAny>;
 
 // Encode modes: ranks within the block; the field-scope mark pass (sort keys
-// of the flattened extrema, nothing encoded); encoding with field-scope ranks.
-enum { kModeBlock = 0, kModeMark = 1, kModeField = 2 };
+// of the flattened extrema, nothing encoded); encoding with field-scope ranks;
+// plain SZp streams (no topology parts: a kernel of its own, so the others
+// carry none of its code).
+enum { kModeBlock = 0, kModeMark = 1, kModeField = 2, kModePlain = 3 };
 
 // Encodes chunk c of the field of `a` (all WAVES waves of the workgroup).
 template <int ND, int WAVES, int MODE = kModeBlock>
@@ -794,7 +796,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
 
   // interior blocks of a topology stream in block scope take block_fast
   // (below) when the field is at least 64 wide
-  const bool fast_mode = g.nx >= kB;
+  const bool fast_mode = (MODE == kModePlain || topo) && g.nx >= kB;
   // a wave whose blocks read only inside the field loads without clamping
   const bool inner = fast_mode && reads_inside<ND>(bw, g) && reads_inside<ND>(bw + BPW - 1, g);
   const unsigned xoff = lane == 0 ? 0u : 65u;
@@ -822,9 +824,13 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     const int xe = x + kB - 1;
     ok = ok && y >= 1 && y + (xe >= g.nx ? 1 : 0) <= g.ny - 2;
     const bool xb = x == 0 || xe >= g.nx - 1;
-    // (plain SZp has no x neighbours to mask: its boundary blocks are fast too)
-    fastm = (unsigned)__ballot(ok && (!xb || !topo));  // lanes >= BPW never set ok
-    xbm = (unsigned)__ballot(ok && xb && topo);
+    if constexpr (MODE == kModePlain) {
+      // plain SZp has no x neighbours to mask: its boundary blocks are fast too
+      fastm = (unsigned)__ballot(ok);  // lanes >= BPW never set ok
+    } else {
+      fastm = (unsigned)__ballot(ok && !xb);
+      xbm = (unsigned)__ballot(ok && xb);
+    }
     l0v = x == 0 ? 0 : g.nx - x;
     l1v = g.nx - 1 - x;
   }
@@ -1034,7 +1040,7 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     mul_round_up2(fmaf(t, 2.0f, -1.0f), fmaf(t, 2.0f, 1.0f), e, lo, hi);
     if (~(__ballot(av >= lo) & __ballot(av < hi) & __ballot(fabsf(t) <= (float)kQMax)) != 0ull) return false;
     const int q = (int)t;
-    if (!topo) {
+    if constexpr (MODE == kModePlain) {
       // plain SZp: the bin indices' residuals, width and planes only
       const unsigned qb = (unsigned)q ^ 0x80000000u;
       const unsigned pb = (unsigned)dpp_from_prev((int)qb, (int)qb);
@@ -1334,50 +1340,39 @@ encode_kernel(EncArgs a) {
 // finding its place in the merged run by one binary search in the other
 // run.
 
-// Exclusive scan of the chunks' counts (one workgroup of 1024 threads):
-// coff[c] = keys of the chunks before c, coff[nch] = all of them.
-__global__ __launch_bounds__(1024) void fs_scan_kernel(const unsigned* __restrict__ ccnt, unsigned* coff, int nch,
-                                                       uint8_t* ws) {
-  __shared__ unsigned s_w[16];
-  __shared__ unsigned s_carry;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) s_carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nch; base += 1024) {
-    const int c = base + tid;
-    const unsigned v = c < nch ? ccnt[c] : 0u;
-    const unsigned incl = (unsigned)wave_incl_scan((int)v, lane);
-    if (lane == 63) s_w[wv] = incl;
-    __syncthreads();
-    unsigned wbase = s_carry;
-    for (int w = 0; w < wv; ++w) wbase += s_w[w];
-    if (c < nch) coff[c] = wbase + incl - v;
-    __syncthreads();
-    if (tid == 1023) s_carry = wbase + incl;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    coff[nch] = s_carry;
-    ctrl_of(ws)->fs_count = s_carry;
-  }
-}
-
 // One workgroup per chunk: its m keys (at most one per point) into LDS, each
 // placed by the count of keys before it (smaller, or equal with a smaller
-// index), and written as the chunk's sorted run at coff[c].
+// index), and written as the chunk's sorted run at coff[c], the keys of the
+// chunks before it, which the workgroup sums itself (coff[nch] = all keys,
+// from the last chunk).
 constexpr int kFsThreads = 256;
 __global__ __launch_bounds__(kFsThreads) void fs_sort_kernel(const unsigned long long* __restrict__ keys,
                                                              const unsigned* __restrict__ vals,
-                                                             const unsigned* __restrict__ ccnt,
-                                                             const unsigned* __restrict__ coff,
-                                                             unsigned long long* okeys, unsigned* ovals) {
+                                                             const unsigned* __restrict__ ccnt, unsigned* coff,
+                                                             int nch, uint8_t* ws, unsigned long long* okeys,
+                                                             unsigned* ovals) {
   __shared__ unsigned long long s_k[kChunk];
-  const int c = blockIdx.x, tid = threadIdx.x;
+  __shared__ unsigned s_part[kFsThreads / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int m = (int)ccnt[c];
   const size_t src = (size_t)c * kChunk;
   for (int e = tid; e < m; e += kFsThreads) s_k[e] = keys[src + e];
+  unsigned part = 0;
+  for (int j = tid; j < c; j += kFsThreads) part += ccnt[j];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += (unsigned)__shfl_xor((int)part, o);
+  if (lane == 0) s_part[tid >> 6] = part;
   __syncthreads();
-  const unsigned base = coff[c];
+  unsigned base = 0;
+#pragma unroll
+  for (int w = 0; w < kFsThreads / 64; ++w) base += s_part[w];
+  if (tid == 0) {
+    coff[c] = base;
+    if (c == nch - 1) {
+      coff[nch] = base + (unsigned)m;
+      ctrl_of(ws)->fs_count = base + (unsigned)m;
+    }
+  }
   for (int e = tid; e < m; e += kFsThreads) {
     const unsigned long long k = s_k[e];
     int pos = 0;
@@ -1485,6 +1480,26 @@ __global__ __launch_bounds__(1024) void fs_merge_lds_kernel(const unsigned long 
   }
 }
 
+// The first index j <= i whose key is >= k (keys sorted, keys[i] >= k), by
+// galloping back from i: steps of 1, 2, 4, ... until a key below k (or
+// index 0), then a binary search in the last step.  The cost follows the
+// distance to the answer (a group or a tie run), not the array's size.
+__device__ __forceinline__ unsigned fs_back(const unsigned long long* __restrict__ keys, unsigned i,
+                                            unsigned long long k) {
+  unsigned hi = i, step = 1;  // keys[hi] >= k
+  unsigned lo = 0;            // lower bound of the search, once a key below k is found
+  while (hi > 0) {
+    const unsigned j = hi > step ? hi - step : 0;
+    if (keys[j] < k) {
+      lo = j + 1;
+      break;
+    }
+    hi = j;
+    step <<= 1;
+  }
+  return fs_bound<false>(keys, lo, hi, k);
+}
+
 // Field-scope ranks from the sorted keys: a flattened extremum's rank is 1 +
 // the number of entries of its (class, bin) group sorted before its value
 // (ties share a rank).  Both starts are lower bounds in the sorted prefix.
@@ -1495,8 +1510,8 @@ __global__ __launch_bounds__(256) void fs_rank_kernel(const unsigned long long* 
   for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
     const unsigned long long k = keys[i];
     const unsigned long long gk = k & ~0xFFFFFFFFull;
-    const unsigned g0 = fs_bound<false>(keys, 0, i, gk);
-    const unsigned t0 = fs_bound<false>(keys, g0, i, k);
+    const unsigned g0 = fs_back(keys, i, gk);
+    const unsigned t0 = fs_back(keys, i, k);
     delta[vals[i]] = (int)(1 + t0 - g0);
   }
 }
@@ -3483,8 +3498,14 @@ __global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t*
   for_items(h->n_chunk, [&](int it) {
     const int f = find_job(pre, h->count, it);
     const CompJob& J = jobs[f];
-    if (J.ndim == 3) encode_body<3, WAVES>(J.enc, it - pre[f], sh);
-    else encode_body<2, WAVES>(J.enc, it - pre[f], sh);
+    if (!J.enc.topo) {
+      if (J.ndim == 3) encode_body<3, WAVES, kModePlain>(J.enc, it - pre[f], sh);
+      else encode_body<2, WAVES, kModePlain>(J.enc, it - pre[f], sh);
+    } else if (J.ndim == 3) {
+      encode_body<3, WAVES>(J.enc, it - pre[f], sh);
+    } else {
+      encode_body<2, WAVES>(J.enc, it - pre[f], sh);
+    }
   });
 }
 
@@ -3805,6 +3826,13 @@ int build_dec(const uint8_t* d_in, size_t in_size, float* d_out, size_t out_cap_
 }
 
 void launch_encode(int ndim, int waves, unsigned grid, hipStream_t s, const EncArgs& ea) {
+  if (!ea.topo) {
+    if (ndim == 3 && waves == 8) hipLaunchKernelGGL((encode_kernel<3, 8, kModePlain>), dim3(grid), dim3(512), 0, s, ea);
+    else if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4, kModePlain>), dim3(grid), dim3(256), 0, s, ea);
+    else if (waves == 8) hipLaunchKernelGGL((encode_kernel<2, 8, kModePlain>), dim3(grid), dim3(512), 0, s, ea);
+    else hipLaunchKernelGGL((encode_kernel<2, 4, kModePlain>), dim3(grid), dim3(256), 0, s, ea);
+    return;
+  }
   if (ndim == 3 && waves == 8) hipLaunchKernelGGL((encode_kernel<3, 8>), dim3(grid), dim3(512), 0, s, ea);
   else if (ndim == 3) hipLaunchKernelGGL((encode_kernel<3, 4>), dim3(grid), dim3(256), 0, s, ea);
   else if (waves == 8) hipLaunchKernelGGL((encode_kernel<2, 8>), dim3(grid), dim3(512), 0, s, ea);
@@ -3995,11 +4023,10 @@ int toposzp_compress(const float* d_field, uint32_t ndim, const uint64_t* dims, 
     auto V = [&](uint64_t o) { return reinterpret_cast<unsigned*>(ws + o); };
     const unsigned* ccnt = V(F.ccnt);
     const unsigned* coff = V(F.coff);
-    hipLaunchKernelGGL(fs_scan_kernel, dim3(1), dim3(1024), 0, s, ccnt, V(F.coff), ea.nch, ws);
     // runs of one chunk into the "out" arrays, then four-way merges back and
     // forth; the sorted keys end where the last pass wrote them
     hipLaunchKernelGGL(fs_sort_kernel, dim3(ea.nch), dim3(kFsThreads), 0, s, K(F.keys_in), V(F.vals_in), ccnt,
-                       coff, K(F.keys_out), V(F.vals_out));
+                       V(F.coff), ea.nch, ws, K(F.keys_out), V(F.vals_out));
     const unsigned mg = (unsigned)std::min<uint64_t>(((uint64_t)hg.g.n + 1023) / 1024, 2048);
     bool in_out = true;  // the current run arrays are the "out" ones
     for (int L = 0; (1ll << (2 * L)) < ea.nch; ++L) {
