@@ -3489,8 +3489,10 @@ __global__ __launch_bounds__(256) void range_batch_kernel(const uint8_t* __restr
   });
 }
 
+// At most 80 VGPRs (six waves per SIMD): both dimensions' bodies in one
+// kernel otherwise take 81-213 VGPRs, and the batch measured 8% faster so.
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t* __restrict__ tab) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(6, 6))) void encode_batch_kernel(const uint8_t* __restrict__ tab) {
   __shared__ EncShared sh;
   const BatchHdr* h = reinterpret_cast<const BatchHdr*>(tab);
   const int* pre = reinterpret_cast<const int*>(tab + sizeof(BatchHdr)) + h->count + 1;
@@ -3498,14 +3500,10 @@ __global__ __launch_bounds__(WAVES * 64) void encode_batch_kernel(const uint8_t*
   for_items(h->n_chunk, [&](int it) {
     const int f = find_job(pre, h->count, it);
     const CompJob& J = jobs[f];
-    if (!J.enc.topo) {
-      if (J.ndim == 3) encode_body<3, WAVES, kModePlain>(J.enc, it - pre[f], sh);
-      else encode_body<2, WAVES, kModePlain>(J.enc, it - pre[f], sh);
-    } else if (J.ndim == 3) {
-      encode_body<3, WAVES>(J.enc, it - pre[f], sh);
-    } else {
-      encode_body<2, WAVES>(J.enc, it - pre[f], sh);
-    }
+    // (plain-SZp jobs take block mode's exact path: instantiating the plain
+    // mode here too measured slower for the whole batch)
+    if (J.ndim == 3) encode_body<3, WAVES>(J.enc, it - pre[f], sh);
+    else encode_body<2, WAVES>(J.enc, it - pre[f], sh);
   });
 }
 
