@@ -764,6 +764,7 @@ struct EncSharedT {
   int pfd[kB + 1], pfr[kB + 1];
   RangeSh rs;
   unsigned wfl[16];  // each wave's error flags
+  unsigned hs[16 * 64];  // each wave's 64 slots for the shared-key test
 };
 
 using EncShared = EncSharedT<kMaxWRankBlk>;
@@ -1125,7 +1126,10 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
     // common case, so the pairwise count runs only when two of them share a
     // bin and class
     int cnt = 0;
-    if (MODE == kModeBlock && (ext & (ext - 1))) {
+    if (MODE == kModeBlock && ND == 3 && (ext & (ext - 1))) {
+      // (3D: the pairwise count over all of them once any two share a bin
+      // and class; the kernel is at its register limit, and the 2D form
+      // below costs it more than it saves)
       const int ck = (q << 1) | (lane_in(m_max) ? 1 : 0);
       unsigned shared = 0;
       unsigned long long m = ext;
@@ -1143,6 +1147,36 @@ __device__ __forceinline__ void encode_body(const EncArgs& a, int c,
           const int ckj = __builtin_amdgcn_readlane(ck, j);
           const int okj = __builtin_amdgcn_readlane(ok, j);
           cnt += (ck == ckj && okj < ok) ? 1 : 0;
+        }
+      }
+    }
+    if (MODE == kModeBlock && ND == 2 && (ext & (ext - 1))) {
+      // the (class, bin) groups one at a time; only the members of a group
+      // of two or more compare their order keys, and only with each other
+      const int ck = (q << 1) | (lane_in(m_max) ? 1 : 0);
+      // two flattened extrema of one (class, bin) land on one of the wave's
+      // 64 LDS slots (the key's low bits): each writes its lane there, and
+      // one of them then reads back another lane; without such a clash the
+      // keys are distinct and every count is 0
+      volatile __attribute__((address_space(3))) unsigned* const hs =
+          (volatile __attribute__((address_space(3))) unsigned*)(sh.hs + wv * 64 + (ck & 63));
+      bool clash = false;
+      if (lane_in(ext)) {
+        *hs = (unsigned)lane;
+        clash = *hs != (unsigned)lane;
+      }
+      const int ok = lane_in(m_max) ? fkey(av) : -fkey(av);
+      unsigned long long m = __ballot(clash) ? ext : 0ull;
+      while (m) {
+        const unsigned long long grp = __ballot(ck == __builtin_amdgcn_readlane(ck, __ffsll((long long)m) - 1)) & ext;
+        m &= ~grp;
+        if ((grp & (grp - 1)) && lane_in(grp)) {
+          unsigned long long mm = grp;
+          while (mm) {
+            const int j = __ffsll((long long)mm) - 1;
+            mm &= ~(1ull << j);
+            cnt += __builtin_amdgcn_readlane(ok, j) < ok ? 1 : 0;
+          }
         }
       }
     }
