@@ -209,6 +209,20 @@ def test_parity_plain_szp(tsz, ora):
     check(tsz, ora, "plain3d_wide", datagen.grf_3d(12, 30, 70, seed=12), 1e-4, "rel", topo=False)
 
 
+def test_parity_rank_groups(tsz, ora):
+    """Block-scope ranks where flattened extrema crowd three bins 32 apart
+    (10, 42, 74 at bin width 1): their (class, bin) keys agree in the low six
+    bits, so distinct keys meet on one slot of the shared-key test, and each
+    block also holds several flattened extrema of one class and bin, whose
+    ranks then exceed 1 (Section IV-A (2))."""
+    rng = np.random.default_rng(21)
+    centres = np.array([10.0, 42.0, 74.0])
+    f2 = (rng.choice(centres, (70, 300)) + rng.uniform(-0.45, 0.45, (70, 300))).astype(np.float32)
+    check(tsz, ora, "rank_groups_2d", f2, 0.5, "abs")
+    f3 = (rng.choice(centres, (10, 12, 90)) + rng.uniform(-0.45, 0.45, (10, 12, 90))).astype(np.float32)
+    check(tsz, ora, "rank_groups_3d", f3, 0.5, "abs")
+
+
 def test_parity_adversarial_values(tsz, ora):
     """Values on and next to bin edges, a power-of-two bound, signed zeros,
     denormals and ties."""
